@@ -1,0 +1,636 @@
+// C-ABI of the helmsweep library: handles, argument checks, and host control of FGMRES.
+// Every arithmetic step of the method runs in the HIP kernels of hs_*.hip; this file only
+// validates arguments, allocates device memory, builds launch descriptors and sequences launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/helmsweep.h"
+#include "hs_common.h"
+#include "hs_kernels.h"
+
+using namespace hs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(HELM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCHCHK()                                                                            \
+    do {                                                                                       \
+        hipError_t e_ = hipGetLastError();                                                     \
+        if (e_ != hipSuccess) return fail(HELM_EHIP, "kernel launch: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+// Device allocation owned by a handle.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    int alloc(size_t b) {
+        release();
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return fail(HELM_ENOMEM, "hipMalloc(%zu bytes): %s", b, hipGetErrorString(e));
+        }
+        bytes = b;
+        return HELM_OK;
+    }
+    template <class T> T* as() const { return (T*)p; }
+};
+
+bool supported_B(int B) { return B == 4 || B == 5 || B == 7 || B == 9 || B == 13 || B == 17; }
+
+constexpr int64_t kMaxN = 32767;
+
+}  // namespace
+
+struct helm_problem_s {
+    helm_params prm{};
+    int n = 0, B = 0, c = 0, L_lo = 0, L_up = 0, nsub = 0;
+    double h = 0;
+    ProfileLayout lay{};
+    DevBuf tab, ic2, pd, flag;
+    ProbDev host{};
+};
+
+struct sweep_factors_s {
+    helm_problem_t A = nullptr;
+    int prec = 0;
+    DevBuf fac, subs, spill, status;
+    int64_t fac_elems = 0;
+    std::vector<SubDev> hsubs;
+    std::vector<int> sub_rows;
+    // single-problem chain tables (rebuilt when nrhs changes)
+    DevBuf chains, mids;
+    int chains_nrhs = -1, nchains = 0, nmids = 0;
+    helm_batch_t solo = nullptr;    // cached batch of one for fgmres_solve
+    int solo_nrhs = -1, solo_restart = -1;
+    ~sweep_factors_s();
+};
+
+struct helm_batch_s {
+    int count = 0, restart = 0, prec = 0, B = 0;
+    std::vector<helm_problem_t> A;
+    std::vector<sweep_factors_t> M;
+    std::vector<int> nrhs;
+    std::vector<int64_t> N;
+    int nsys = 0, ntiles = 0, mv_blocks = 0, nchains = 0, nmids = 0;
+    std::vector<int> sys_prob, sys_rhs;
+    std::vector<int32_t> tiles_h;
+    DevBuf probs, chains, mids, io_sweep, io_apply, mv_z, mv_res, mv_blk, sv, tiles;
+    DevBuf V, Z, W, spill;
+    DevBuf H, cs, g, y, partial, hbuf, nrm, inv, est, fnorm, beta, active, cnt;
+    std::vector<int64_t> voff, zoff, woff;   // element offsets of each problem's blocks
+    size_t zelem = 16;
+};
+
+sweep_factors_s::~sweep_factors_s() {
+    if (solo) helm_batch_free(solo);
+}
+
+// ------------------------------------------------------------------------------------------------
+extern "C" const char* helm_version(void) { return "helmsweep 0.1 (gfx950)"; }
+extern "C" const char* helm_last_error(void) { return g_err.c_str(); }
+
+static int check_params(const helm_params* p, int* Bout) {
+    if (!p) return fail(HELM_EINVAL, "params is NULL");
+    if (p->b_convention != 0 && p->b_convention != 1) return fail(HELM_EINVAL, "b_convention must be 0 or 1");
+    if (p->pml_w < 1 || p->mpml_w < 1) return fail(HELM_EINVAL, "pml_w and mpml_w must be >= 1");
+    const int B = p->b_convention == 0 ? p->mpml_w + 1 : p->mpml_w;
+    if (!supported_B(B)) return fail(HELM_EINVAL, "strip height B=%d not compiled (supported 4,5,7,9,13,17)", B);
+    if (p->n < 2 * B + 3) return fail(HELM_EINVAL, "n=%d too small for B=%d (need n >= 2B+3)", p->n, B);
+    if (p->n > kMaxN) return fail(HELM_EINVAL, "n=%d exceeds %lld", p->n, (long long)kMaxN);
+    if (!(p->omega > 0.0) || !std::isfinite(p->omega)) return fail(HELM_EINVAL, "omega must be finite and > 0");
+    if (!(p->alpha >= 0.0) || !std::isfinite(p->alpha)) return fail(HELM_EINVAL, "alpha must be finite and >= 0");
+    if (!(p->pml_C > 0.0) || !std::isfinite(p->pml_C)) return fail(HELM_EINVAL, "pml_C must be finite and > 0");
+    const int wp = p->b_convention == 0 ? p->pml_w + 1 : p->pml_w;
+    if (2 * wp > p->n + 1) return fail(HELM_EINVAL, "physical PML wider than half the domain");
+    *Bout = B;
+    return HELM_OK;
+}
+
+extern "C" int helm_assemble(const helm_params* p, const double* c, void* stream, helm_problem_t* out) {
+    int B = 0;
+    int rc = check_params(p, &B);
+    if (rc) return rc;
+    if (!c || !out) return fail(HELM_EINVAL, "c or out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<helm_problem_s> A(new helm_problem_s());
+    A->prm = *p;
+    const int n = p->n;
+    A->n = n; A->B = B;
+    A->c = (n % 2 == 1) ? (n + 1) / 2 : n / 2 + 1;
+    A->L_lo = A->c - 1 - B;
+    A->L_up = n - B - A->c;
+    A->nsub = A->L_lo + A->L_up + 3;
+    A->h = 1.0 / (n + 1);
+    A->lay = ProfileLayout::make(n, B);
+    const int64_t N = (int64_t)n * n;
+    if ((rc = A->tab.alloc(sizeof(double2) * A->lay.total))) return rc;
+    if ((rc = A->ic2.alloc(sizeof(double) * N))) return rc;
+    if ((rc = A->flag.alloc(sizeof(int)))) return rc;
+    if ((rc = A->pd.alloc(sizeof(ProbDev)))) return rc;
+    HIPCHK(hipMemsetAsync(A->flag.p, 0, sizeof(int), s));
+    const double h = A->h;
+    const double eta_p = (p->b_convention == 0 ? p->pml_w + 1 : p->pml_w) * h;
+    const double eta_m = B * h;
+    launch_profiles(A->lay, A->tab.as<double2>(), h, p->omega, eta_p, eta_m, p->pml_C, s);
+    LAUNCHCHK();
+    launch_inv_c2(c, A->ic2.as<double>(), N, A->flag.as<int>(), s);
+    LAUNCHCHK();
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, A->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) return fail(HELM_EINVAL, "velocity c has a non-finite or non-positive value");
+    ProbDev& P = A->host;
+    P.n = n; P.B = B; P.c = A->c; P.L_lo = A->L_lo; P.L_up = A->L_up; P.nsub = A->nsub;
+    P.ih2 = 1.0 / (h * h);
+    const double kr = p->omega, ki = p->alpha;
+    P.kappa2 = make_double2(kr * kr - ki * ki, 2.0 * kr * ki);
+    P.omega2 = make_double2(kr * kr, 0.0);
+    double2* t = A->tab.as<double2>();
+    const ProfileLayout& L = A->lay;
+    P.s1n = t + L.s1n; P.is1n = t + L.is1n; P.s1h = t + L.s1h;
+    P.s2n = t + L.s2n; P.is2n = t + L.is2n; P.s2h = t + L.s2h;
+    P.mvn = t + L.mvn; P.imvn = t + L.imvn; P.mvh = t + L.mvh;
+    P.mdn = t + L.mdn; P.imdn = t + L.imdn; P.mdh = t + L.mdh;
+    P.ic2 = A->ic2.as<double>();
+    HIPCHK(hipMemcpy(A->pd.p, &P, sizeof(ProbDev), hipMemcpyHostToDevice));
+    *out = A.release();
+    return HELM_OK;
+}
+
+extern "C" int helm_problem_n(helm_problem_t A) { return A ? A->n : -1; }
+
+extern "C" void helm_free(helm_problem_t A) { delete A; }
+
+extern "C" int helm_matvec(helm_problem_t A, const void* x, int32_t x_prec, void* y, int32_t nrhs, void* stream) {
+    if (!A || !x || !y) return fail(HELM_EINVAL, "NULL argument");
+    if (nrhs < 0) return fail(HELM_EINVAL, "nrhs < 0");
+    if (x_prec != HELM_C128 && x_prec != HELM_C64) return fail(HELM_EINVAL, "x_prec must be HELM_C128 or HELM_C64");
+    if (nrhs == 0) return HELM_OK;
+    MvDev mv{x, y, nullptr, nrhs, 0};
+    launch_matvec(A->pd.as<ProbDev>(), nullptr, mv, nullptr, 1, matvec_blocks(A->n), x_prec, (hipStream_t)stream);
+    LAUNCHCHK();
+    return HELM_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// a2: factorisation
+// ------------------------------------------------------------------------------------------------
+extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_factors_t* out) {
+    if (!A || !out) return fail(HELM_EINVAL, "NULL argument");
+    if (prec != HELM_C128 && prec != HELM_C64) return fail(HELM_EINVAL, "prec must be HELM_C128 or HELM_C64");
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<sweep_factors_s> M(new sweep_factors_s());
+    M->A = A;
+    M->prec = prec;
+    const int n = A->n, B = A->B;
+    const int64_t pk = packed_size(B), pkm = packed_size(2 * B - 1);
+    M->fac_elems = (int64_t)(A->nsub - 1) * n * pk + (int64_t)n * pkm;
+    const size_t esz = prec == HELM_C128 ? sizeof(double2) : sizeof(float2);
+    int rc;
+    if ((rc = M->fac.alloc(esz * (size_t)M->fac_elems))) return rc;
+    // strip descriptors: F, lower layers, E, upper layers (all height B), then the middle (2B-1)
+    auto& S = M->hsubs;
+    S.clear();
+    for (int t = 0; t <= A->L_lo; ++t) {
+        const int jl = B + t;
+        S.push_back(SubDev{0, t == 0 ? SUB_PHYS : SUB_MOVE, jl - (B - 1), 1, (int64_t)S.size() * n * pk});
+    }
+    for (int t = 0; t <= A->L_up; ++t) {
+        const int jl = n + 1 - B - t;
+        S.push_back(SubDev{0, t == 0 ? SUB_PHYS : SUB_MOVE, jl + (B - 1), -1, (int64_t)S.size() * n * pk});
+    }
+    S.push_back(SubDev{0, SUB_MID, A->c - B + 1, 1, (int64_t)S.size() * n * pk});
+    M->sub_rows.assign(S.size(), B);
+    M->sub_rows.back() = 2 * B - 1;
+    if ((int)S.size() != A->nsub) return fail(HELM_EINVAL, "internal: subproblem count");
+    if ((rc = M->subs.alloc(sizeof(SubDev) * S.size()))) return rc;
+    if ((rc = M->status.alloc(sizeof(int)))) return rc;
+    HIPCHK(hipMemcpy(M->subs.p, S.data(), sizeof(SubDev) * S.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemsetAsync(M->status.p, 0, sizeof(int), s));
+    const ProbDev* pd = A->pd.as<ProbDev>();
+    if (!launch_factor(B, prec, pd, M->subs.as<SubDev>(), A->nsub - 1, n, M->fac.p, M->status.as<int>(), s))
+        return fail(HELM_EINVAL, "no factor kernel for B=%d", B);
+    LAUNCHCHK();
+    if (!launch_factor(2 * B - 1, prec, pd, M->subs.as<SubDev>() + (A->nsub - 1), 1, n, M->fac.p, M->status.as<int>(), s))
+        return fail(HELM_EINVAL, "no factor kernel for middle height %d", 2 * B - 1);
+    LAUNCHCHK();
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, M->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) return fail(HELM_ESINGULAR, "zero or non-finite pivot while inverting a diagonal block");
+    *out = M.release();
+    return HELM_OK;
+}
+
+extern "C" int64_t sweep_factor_bytes(sweep_factors_t M) { return M ? (int64_t)M->fac.bytes : 0; }
+extern "C" int sweep_num_subproblems(sweep_factors_t M) { return M ? (int)M->hsubs.size() : -1; }
+extern "C" int sweep_subproblem_rows(sweep_factors_t M, int32_t sub) {
+    if (!M || sub < 0 || sub >= (int)M->sub_rows.size()) return -1;
+    return M->sub_rows[sub];
+}
+
+extern "C" void sweep_free(sweep_factors_t M) { delete M; }
+
+static size_t compute_elem(int prec) { return prec == HELM_C128 ? sizeof(double2) : sizeof(float2); }
+
+// Single-problem chain tables: groups of Q right-hand sides per front, Qm per middle wave.
+static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
+    helm_problem_t A = M->A;
+    const int n = A->n, B = A->B;
+    const int Q = chain_rhs_per_wave(B), Qm = middle_rhs_per_wave(B);
+    const int groups = (nrhs + Q - 1) / Q, mgroups = (nrhs + Qm - 1) / Qm;
+    const int64_t per = (int64_t)n * 64;
+    const size_t need = compute_elem(M->prec) * (size_t)per * (size_t)std::max(2 * groups, mgroups);
+    int rc;
+    if (M->spill.bytes < need) {
+        HIPCHK(hipStreamSynchronize(s));
+        if ((rc = M->spill.alloc(need))) return rc;
+    }
+    if (M->chains_nrhs == nrhs) return HELM_OK;
+    std::vector<ChainDev> ch, md;
+    for (int g = 0; g < groups; ++g)
+        for (int f = 0; f < 2; ++f)
+            ch.push_back(ChainDev{0, f, g * Q, std::min(Q, nrhs - g * Q), (int64_t)ch.size() * per});
+    for (int g = 0; g < mgroups; ++g) md.push_back(ChainDev{0, 0, g * Qm, std::min(Qm, nrhs - g * Qm), (int64_t)g * per});
+    HIPCHK(hipStreamSynchronize(s));
+    if ((rc = M->chains.alloc(sizeof(ChainDev) * ch.size()))) return rc;
+    if ((rc = M->mids.alloc(sizeof(ChainDev) * md.size()))) return rc;
+    HIPCHK(hipMemcpy(M->chains.p, ch.data(), sizeof(ChainDev) * ch.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(M->mids.p, md.data(), sizeof(ChainDev) * md.size(), hipMemcpyHostToDevice));
+    M->nchains = (int)ch.size();
+    M->nmids = (int)md.size();
+    M->chains_nrhs = nrhs;
+    return HELM_OK;
+}
+
+extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nrhs, int32_t vec_prec, void* stream) {
+    if (!M || !f || !u) return fail(HELM_EINVAL, "NULL argument");
+    if (nrhs < 0) return fail(HELM_EINVAL, "nrhs < 0");
+    if (vec_prec != HELM_C128 && vec_prec != HELM_C64) return fail(HELM_EINVAL, "vec_prec must be HELM_C128 or HELM_C64");
+    if (M->prec == HELM_C128 && vec_prec != HELM_C128) return fail(HELM_EINVAL, "complex128 factors need complex128 vectors");
+    if (nrhs == 0) return HELM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_solo_chains(M, nrhs, s);
+    if (rc) return rc;
+    const ProbDev* pd = M->A->pd.as<ProbDev>();
+    IoDev io{f, u, M->fac.p};
+    const int B = M->A->B;
+    if (!launch_chains(B, M->prec, vec_prec, vec_prec, 0, pd, M->chains.as<ChainDev>(), M->nchains, nullptr, io, M->spill.p, s))
+        return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
+    LAUNCHCHK();
+    launch_middle(B, M->prec, vec_prec, vec_prec, pd, M->mids.as<ChainDev>(), M->nmids, nullptr, io, M->spill.p, s);
+    LAUNCHCHK();
+    launch_chains(B, M->prec, vec_prec, vec_prec, 1, pd, M->chains.as<ChainDev>(), M->nchains, nullptr, io, M->spill.p, s);
+    LAUNCHCHK();
+    return HELM_OK;
+}
+
+extern "C" int sweep_subsolve(sweep_factors_t M, int32_t sub, const void* g, void* x, int32_t nrhs, void* stream) {
+    if (!M || !g || !x) return fail(HELM_EINVAL, "NULL argument");
+    if (sub < 0 || sub >= (int)M->hsubs.size()) return fail(HELM_EINVAL, "subproblem index out of range");
+    if (nrhs <= 0) return nrhs == 0 ? HELM_OK : fail(HELM_EINVAL, "nrhs < 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int bs = M->sub_rows[sub];
+    const int Q = 64 / chain_padded_rows(bs);
+    const int groups = (nrhs + Q - 1) / Q;
+    const size_t need = compute_elem(M->prec) * (size_t)M->A->n * 64 * groups;
+    int rc;
+    if (M->spill.bytes < need) {
+        HIPCHK(hipStreamSynchronize(s));
+        if ((rc = M->spill.alloc(need))) return rc;
+    }
+    const SubDev& S = M->hsubs[sub];
+    const size_t esz = M->prec == HELM_C128 ? sizeof(double2) : sizeof(float2);
+    const char* fac = (const char*)M->fac.p + esz * S.fac_off;
+    if (!launch_subsolve(bs, M->prec, M->A->pd.as<ProbDev>(), fac, S.kind, S.j0, S.dir, g, x, nrhs, M->spill.p, s))
+        return fail(HELM_EINVAL, "no strip kernel for height %d", bs);
+    LAUNCHCHK();
+    return HELM_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// a6 / a7: batched FGMRES
+// ------------------------------------------------------------------------------------------------
+extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t* M, const int32_t* nrhs, int32_t count,
+                                 int32_t restart, void* stream, helm_batch_t* out) {
+    if (!A || !M || !nrhs || !out) return fail(HELM_EINVAL, "NULL argument");
+    if (count <= 0) return fail(HELM_EINVAL, "count must be > 0");
+    if (restart < 1 || restart > 256) return fail(HELM_EINVAL, "restart must be in [1, 256]");
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<helm_batch_s> b(new helm_batch_s());
+    b->count = count;
+    b->restart = restart;
+    for (int k = 0; k < count; ++k) {
+        if (!A[k] || !M[k]) return fail(HELM_EINVAL, "NULL handle at %d", k);
+        if (M[k]->A != A[k]) return fail(HELM_EINVAL, "factors %d do not belong to problem %d", k, k);
+        if (nrhs[k] < 1) return fail(HELM_EINVAL, "nrhs[%d] must be >= 1", k);
+        if (k > 0 && (A[k]->B != A[0]->B || M[k]->prec != M[0]->prec))
+            return fail(HELM_EINVAL, "batch members must share B and factor precision");
+        b->A.push_back(A[k]);
+        b->M.push_back(M[k]);
+        b->nrhs.push_back(nrhs[k]);
+        b->N.push_back((int64_t)A[k]->n * A[k]->n);
+    }
+    b->prec = M[0]->prec;
+    b->B = A[0]->B;
+    const int kk = restart, B = b->B;
+    b->zelem = b->prec == HELM_C128 ? sizeof(double2) : sizeof(float2);
+    // vector storage: V [k+1][R][N], Z [k][R][N], W [R][N] per problem
+    int64_t vo = 0, zo = 0, wo = 0;
+    for (int p = 0; p < count; ++p) {
+        b->voff.push_back(vo); b->zoff.push_back(zo); b->woff.push_back(wo);
+        vo += (int64_t)(kk + 1) * b->nrhs[p] * b->N[p];
+        zo += (int64_t)kk * b->nrhs[p] * b->N[p];
+        wo += (int64_t)b->nrhs[p] * b->N[p];
+    }
+    int rc;
+    if ((rc = b->V.alloc(sizeof(double2) * vo))) return rc;
+    if ((rc = b->Z.alloc(b->zelem * zo))) return rc;
+    if ((rc = b->W.alloc(sizeof(double2) * wo))) return rc;
+    // problems table
+    std::vector<ProbDev> pdv;
+    for (int p = 0; p < count; ++p) pdv.push_back(A[p]->host);
+    if ((rc = b->probs.alloc(sizeof(ProbDev) * count))) return rc;
+    HIPCHK(hipMemcpy(b->probs.p, pdv.data(), sizeof(ProbDev) * count, hipMemcpyHostToDevice));
+    // chains (longest first), middles
+    const int Q = chain_rhs_per_wave(B), Qm = middle_rhs_per_wave(B);
+    std::vector<int> order(count);
+    for (int p = 0; p < count; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return A[a]->n > A[c]->n; });
+    std::vector<ChainDev> ch, md;
+    int64_t so = 0;
+    for (int p : order)
+        for (int g = 0; g * Q < b->nrhs[p]; ++g)
+            for (int f = 0; f < 2; ++f) {
+                ch.push_back(ChainDev{p, f, g * Q, std::min(Q, b->nrhs[p] - g * Q), so});
+                so += (int64_t)A[p]->n * 64;
+            }
+    int64_t mo = 0;
+    for (int p : order)
+        for (int g = 0; g * Qm < b->nrhs[p]; ++g) {
+            md.push_back(ChainDev{p, 0, g * Qm, std::min(Qm, b->nrhs[p] - g * Qm), mo});
+            mo += (int64_t)A[p]->n * 64;
+        }
+    b->nchains = (int)ch.size();
+    b->nmids = (int)md.size();
+    if ((rc = b->chains.alloc(sizeof(ChainDev) * ch.size()))) return rc;
+    if ((rc = b->mids.alloc(sizeof(ChainDev) * md.size()))) return rc;
+    HIPCHK(hipMemcpy(b->chains.p, ch.data(), sizeof(ChainDev) * ch.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->mids.p, md.data(), sizeof(ChainDev) * md.size(), hipMemcpyHostToDevice));
+    if ((rc = b->spill.alloc(compute_elem(b->prec) * (size_t)std::max(so, mo)))) return rc;
+    // io tables for V_j -> Z_j, and matvec tables Z_j -> W
+    std::vector<IoDev> ios((size_t)kk * count);
+    std::vector<MvDev> mvz((size_t)kk * count);
+    double2* V = b->V.as<double2>();
+    char* Z = b->Z.as<char>();
+    double2* W = b->W.as<double2>();
+    for (int j = 0; j < kk; ++j)
+        for (int p = 0; p < count; ++p) {
+            const int64_t blk = (int64_t)b->nrhs[p] * b->N[p];
+            ios[(size_t)j * count + p] = IoDev{V + b->voff[p] + j * blk, Z + b->zelem * (b->zoff[p] + j * blk), M[p]->fac.p};
+            mvz[(size_t)j * count + p] = MvDev{Z + b->zelem * (b->zoff[p] + j * blk), W + b->woff[p], nullptr, b->nrhs[p], 0};
+        }
+    if ((rc = b->io_sweep.alloc(sizeof(IoDev) * ios.size()))) return rc;
+    if ((rc = b->mv_z.alloc(sizeof(MvDev) * mvz.size()))) return rc;
+    if ((rc = b->io_apply.alloc(sizeof(IoDev) * count))) return rc;
+    if ((rc = b->mv_res.alloc(sizeof(MvDev) * count))) return rc;
+    HIPCHK(hipMemcpy(b->io_sweep.p, ios.data(), sizeof(IoDev) * ios.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->mv_z.p, mvz.data(), sizeof(MvDev) * mvz.size(), hipMemcpyHostToDevice));
+    std::vector<int32_t> blk(count + 1);
+    int tot = 0;
+    for (int p = 0; p < count; ++p) { blk[p] = tot; tot += matvec_blocks(A[p]->n); }
+    blk[count] = tot;
+    b->mv_blocks = tot;
+    if ((rc = b->mv_blk.alloc(sizeof(int32_t) * (count + 1)))) return rc;
+    HIPCHK(hipMemcpy(b->mv_blk.p, blk.data(), sizeof(int32_t) * (count + 1), hipMemcpyHostToDevice));
+    // systems and tiles
+    for (int p = 0; p < count; ++p)
+        for (int q = 0; q < b->nrhs[p]; ++q) { b->sys_prob.push_back(p); b->sys_rhs.push_back(q); }
+    b->nsys = (int)b->sys_prob.size();
+    int nt = 0;
+    for (int sidx = 0; sidx < b->nsys; ++sidx) {
+        b->tiles_h.push_back(nt);
+        nt += (int)((b->N[b->sys_prob[sidx]] + KR_TILE - 1) / KR_TILE);
+    }
+    b->tiles_h.push_back(nt);
+    b->ntiles = nt;
+    const int ns = b->nsys;
+    if ((rc = b->tiles.alloc(sizeof(int32_t) * (ns + 1)))) return rc;
+    HIPCHK(hipMemcpy(b->tiles.p, b->tiles_h.data(), sizeof(int32_t) * (ns + 1), hipMemcpyHostToDevice));
+    if ((rc = b->sv.alloc(sizeof(SysVec) * ns))) return rc;
+    if ((rc = b->H.alloc(sizeof(double2) * (size_t)ns * kk * (kk + 1)))) return rc;
+    if ((rc = b->cs.alloc(sizeof(double2) * (size_t)ns * 2 * kk))) return rc;
+    if ((rc = b->g.alloc(sizeof(double2) * (size_t)ns * (kk + 1)))) return rc;
+    if ((rc = b->y.alloc(sizeof(double2) * (size_t)ns * kk))) return rc;
+    if ((rc = b->partial.alloc(sizeof(double2) * (size_t)nt * (kk + 1)))) return rc;
+    if ((rc = b->hbuf.alloc(sizeof(double2) * (size_t)ns * (kk + 1)))) return rc;
+    for (DevBuf* d : {&b->nrm, &b->inv, &b->est, &b->fnorm, &b->beta})
+        if ((rc = d->alloc(sizeof(double) * ns))) return rc;
+    if ((rc = b->active.alloc(sizeof(int32_t) * ns))) return rc;
+    if ((rc = b->cnt.alloc(sizeof(int32_t) * ns))) return rc;
+    (void)s;
+    *out = b.release();
+    return HELM_OK;
+}
+
+extern "C" void helm_batch_free(helm_batch_t b) { delete b; }
+
+// Enqueue M_alpha on the batch: io table `io` (device, one entry per problem), in complex128,
+// out complex128 or complex64 (the factor precision for FGMRES directions).
+static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, hipStream_t s) {
+    const ProbDev* pd = b->probs.as<ProbDev>();
+    const IoDev none{nullptr, nullptr, nullptr};
+    if (!launch_chains(b->B, b->prec, 0, out_prec, 0, pd, b->chains.as<ChainDev>(), b->nchains, io, none, b->spill.p, s))
+        return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
+    LAUNCHCHK();
+    launch_middle(b->B, b->prec, 0, out_prec, pd, b->mids.as<ChainDev>(), b->nmids, io, none, b->spill.p, s);
+    LAUNCHCHK();
+    launch_chains(b->B, b->prec, 0, out_prec, 1, pd, b->chains.as<ChainDev>(), b->nchains, io, none, b->spill.p, s);
+    LAUNCHCHK();
+    return HELM_OK;
+}
+
+extern "C" int sweep_apply_batch(helm_batch_t b, const void* const* f, void* const* u, void* stream) {
+    if (!b || !f || !u) return fail(HELM_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<IoDev> io(b->count);
+    for (int p = 0; p < b->count; ++p) {
+        if (!f[p] || !u[p]) return fail(HELM_EINVAL, "NULL vector for problem %d", p);
+        io[p] = IoDev{f[p], u[p], b->M[p]->fac.p};
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(b->io_apply.p, io.data(), sizeof(IoDev) * b->count, hipMemcpyHostToDevice));
+    return batch_sweep(b, b->io_apply.as<IoDev>(), 0, s);
+}
+
+extern "C" int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* const* u, double tol, int32_t maxit,
+                                  int32_t* iters, double* relres, void* stream) {
+    if (!b || !f || !u) return fail(HELM_EINVAL, "NULL argument");
+    if (!(tol > 0.0 && tol < 1.0)) return fail(HELM_EINVAL, "tol must be in (0, 1)");
+    if (maxit < 1) return fail(HELM_EINVAL, "maxit must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const int ns = b->nsys, kk = b->restart, nt = b->ntiles;
+    // per-call vector tables
+    std::vector<SysVec> sv(ns);
+    std::vector<MvDev> mvr(b->count);
+    for (int p = 0; p < b->count; ++p) {
+        if (!f[p] || !u[p]) return fail(HELM_EINVAL, "NULL vector for problem %d", p);
+        mvr[p] = MvDev{u[p], b->W.as<double2>() + b->woff[p], f[p], b->nrhs[p], 0};
+    }
+    for (int sidx = 0; sidx < ns; ++sidx) {
+        const int p = b->sys_prob[sidx], q = b->sys_rhs[sidx];
+        const int64_t Np = b->N[p], R = b->nrhs[p];
+        SysVec& v = sv[sidx];
+        v.v = b->V.as<double2>() + b->voff[p] + q * Np;
+        v.z = b->Z.as<char>() + b->zelem * (b->zoff[p] + q * Np);
+        v.w = b->W.as<double2>() + b->woff[p] + q * Np;
+        v.x = (double2*)u[p] + q * Np;
+        v.f = (const double2*)f[p] + q * Np;
+        v.len = Np;
+        v.vstride = R * Np;
+        v.zstride = R * Np;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(b->sv.p, sv.data(), sizeof(SysVec) * ns, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->mv_res.p, mvr.data(), sizeof(MvDev) * b->count, hipMemcpyHostToDevice));
+    const SysVec* dsv = b->sv.as<SysVec>();
+    const int32_t* dt = b->tiles.as<int32_t>();
+    const ProbDev* pd = b->probs.as<ProbDev>();
+    const MvDev none{nullptr, nullptr, nullptr, 0, 0};
+    const int zprec = b->prec == HELM_C128 ? 0 : 1;
+
+    std::vector<double> fn(ns), bet(ns), est(ns);
+    std::vector<int32_t> it(ns, 0), done(ns, 0), act(ns, 0), cnt(ns, 0);
+    std::vector<double> rr(ns, 0.0);
+    launch_norms(dsv, dt, ns, nt, 1, b->partial.as<double2>(), b->fnorm.as<double>(), nullptr, s);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(fn.data(), b->fnorm.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < ns; ++i)
+        if (!std::isfinite(fn[i])) return fail(HELM_EINVAL, "right-hand side %d has non-finite values", i);
+
+    const int hstride = kk + 1;
+    while (true) {
+        // r = f - A u (into W), beta = ||r||
+        launch_matvec(pd, b->mv_res.as<MvDev>(), none, b->mv_blk.as<int32_t>(), b->count, b->mv_blocks, 0, s);
+        LAUNCHCHK();
+        launch_norms(dsv, dt, ns, nt, 0, b->partial.as<double2>(), b->beta.as<double>(), nullptr, s);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(bet.data(), b->beta.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int nact = 0;
+        for (int i = 0; i < ns; ++i) {
+            rr[i] = fn[i] > 0.0 ? bet[i] / fn[i] : 0.0;
+            if (!std::isfinite(rr[i])) return fail(HELM_EINVAL, "non-finite residual (system %d)", i);
+            done[i] = (rr[i] <= tol) || fn[i] == 0.0;
+            act[i] = !done[i] && it[i] < maxit;
+            cnt[i] = 0;
+            nact += act[i];
+        }
+        if (nact == 0) break;
+        HIPCHK(hipMemcpyAsync(b->active.p, act.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+        launch_start_cycle(ns, b->beta.as<double>(), b->inv.as<double>(), b->g.as<double2>(), kk + 1, s);
+        LAUNCHCHK();
+        launch_scale_to_v(dsv, dt, ns, nt, 0, b->inv.as<double>(), b->active.as<int32_t>(), s);
+        LAUNCHCHK();
+        for (int j = 0; j < kk; ++j) {
+            int rc = batch_sweep(b, b->io_sweep.as<IoDev>() + (size_t)j * b->count, zprec, s);
+            if (rc) return rc;
+            launch_matvec(pd, b->mv_z.as<MvDev>() + (size_t)j * b->count, none, b->mv_blk.as<int32_t>(), b->count,
+                          b->mv_blocks, zprec, s);
+            LAUNCHCHK();
+            double2* Hcol = b->H.as<double2>() + (size_t)j * (kk + 1);   // system stride kk*(kk+1)
+            const int hs_ = kk * (kk + 1);
+            // classical Gram-Schmidt, twice
+            launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, b->active.as<int32_t>(), s);
+            launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 0, s);
+            launch_multiaxpy(dsv, dt, ns, nt, j, Hcol, hs_, b->active.as<int32_t>(), s);
+            launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, b->active.as<int32_t>(), s);
+            launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, b->hbuf.as<double2>(), hstride, 0, s);
+            launch_multiaxpy(dsv, dt, ns, nt, j, b->hbuf.as<double2>(), hstride, b->active.as<int32_t>(), s);
+            launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 1, s);
+            launch_norms(dsv, dt, ns, nt, 0, b->partial.as<double2>(), b->nrm.as<double>(), b->active.as<int32_t>(), s);
+            launch_arnoldi_finish(ns, j, kk, b->H.as<double2>(), b->cs.as<double2>(), b->g.as<double2>(),
+                                  b->nrm.as<double>(), b->inv.as<double>(), b->est.as<double>(), b->active.as<int32_t>(), s);
+            launch_scale_to_v(dsv, dt, ns, nt, j + 1, b->inv.as<double>(), b->active.as<int32_t>(), s);
+            LAUNCHCHK();
+            HIPCHK(hipMemcpyAsync(est.data(), b->est.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            int still = 0;
+            for (int i = 0; i < ns; ++i) {
+                if (!act[i]) continue;
+                it[i] += 1;
+                cnt[i] = j + 1;
+                const double e = est[i] / fn[i];
+                if (!(e > tol) || it[i] >= maxit) act[i] = 0;   // NaN estimate also ends the cycle
+                still += act[i];
+            }
+            if (still == 0 || j == kk - 1) break;
+            HIPCHK(hipMemcpyAsync(b->active.p, act.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+        }
+        HIPCHK(hipMemcpyAsync(b->cnt.p, cnt.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+        launch_backsolve(ns, kk, b->H.as<double2>(), b->g.as<double2>(), b->cnt.as<int32_t>(), b->y.as<double2>(), s);
+        launch_update_x(dsv, dt, ns, nt, b->cnt.as<int32_t>(), b->y.as<double2>(), kk, zprec, s);
+        LAUNCHCHK();
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    bool all = true;
+    for (int i = 0; i < ns; ++i) {
+        if (iters) iters[i] = it[i];
+        if (relres) relres[i] = rr[i];
+        all = all && done[i];
+    }
+    return all ? HELM_OK : fail(HELM_ENOTCONV, "maxit reached before tol");
+}
+
+extern "C" int fgmres_solve(helm_problem_t A, sweep_factors_t M, const void* f, void* u, int32_t nrhs, int32_t restart,
+                            double tol, int32_t maxit, int32_t* iters, double* relres, void* stream) {
+    if (!A || !M || !f || !u) return fail(HELM_EINVAL, "NULL argument");
+    if (M->A != A) return fail(HELM_EINVAL, "factors do not belong to this problem");
+    if (nrhs < 1) return fail(HELM_EINVAL, "nrhs must be >= 1");
+    if (!M->solo || M->solo_nrhs != nrhs || M->solo_restart != restart) {
+        if (M->solo) { helm_batch_free(M->solo); M->solo = nullptr; }
+        int rc = helm_batch_create(&A, &M, &nrhs, 1, restart, stream, &M->solo);
+        if (rc) return rc;
+        M->solo_nrhs = nrhs;
+        M->solo_restart = restart;
+    }
+    return fgmres_solve_batch(M->solo, &f, &u, tol, maxit, iters, relres, stream);
+}

@@ -1,0 +1,118 @@
+// Shared device-side definitions of the helmsweep library (gfx950).
+//
+// Complex numbers are HIP vector pairs (x = re, y = im): double2 for complex128, float2 for
+// complex64.  Problem, subproblem and chain descriptors live in device memory so that one launch
+// can serve a whole batch of problems of different sizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hs {
+
+// ---------------------------------------------------------------------------------------------
+// complex arithmetic
+// ---------------------------------------------------------------------------------------------
+template <class T> struct c2;
+template <> struct c2<double> { using t = double2; };
+template <> struct c2<float> { using t = float2; };
+template <class T> using C2 = typename c2<T>::t;
+
+template <class T> __host__ __device__ __forceinline__ C2<T> mk(T re, T im) { C2<T> z; z.x = re; z.y = im; return z; }
+template <class T> __host__ __device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <class T> __host__ __device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <class T> __host__ __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// acc + a*b
+template <class T> __host__ __device__ __forceinline__ C2<T> cfma(C2<T> a, C2<T> b, C2<T> acc) {
+    acc.x = fma(a.x, b.x, acc.x); acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y); acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc - a*b
+template <class T> __host__ __device__ __forceinline__ C2<T> cfms(C2<T> a, C2<T> b, C2<T> acc) {
+    acc.x = fma(-a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y); acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+// conj(a) * b
+template <class T> __host__ __device__ __forceinline__ C2<T> cconjmul(C2<T> a, C2<T> b) {
+    return mk<T>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+template <class T> __host__ __device__ __forceinline__ T cabs2(C2<T> a) { return a.x * a.x + a.y * a.y; }
+template <class T> __host__ __device__ __forceinline__ C2<T> cinv(C2<T> a) {
+    // 1/a with scaling against overflow / underflow of |a|^2
+    T s = fmax(fabs(a.x), fabs(a.y));
+    T ar = a.x / s, ai = a.y / s;
+    T d = s * (ar * ar + ai * ai);
+    return mk<T>(ar / d, -ai / d);
+}
+template <class T> __host__ __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+template <class To, class Ti> __host__ __device__ __forceinline__ C2<To> ccast(C2<Ti> a) {
+    return mk<To>((To)a.x, (To)a.y);
+}
+
+// ---------------------------------------------------------------------------------------------
+// descriptors
+// ---------------------------------------------------------------------------------------------
+enum SubKind : int32_t { SUB_PHYS = 0, SUB_MOVE = 1, SUB_MID = 2 };
+
+// One problem: grid size, strip height, shifted wave number and the FP64 profile tables
+// (all device pointers into one allocation owned by the problem handle).
+struct ProbDev {
+    int32_t n, B, c, L_lo, L_up, nsub;  // c: middle layer; L_lo/L_up: moving layers per front
+    double ih2;                         // 1/h^2
+    double2 kappa2;                     // (omega + i alpha)^2   (operator A_alpha)
+    double2 omega2;                     // omega^2               (operator A)
+    const double2 *s1n, *is1n, *s1h;    // x1: s, 1/s at ih (n); s at (i+1/2)h, i = 0..n (n+1)
+    const double2 *s2n, *is2n, *s2h;    // x2 physical, same layout
+    const double2 *mvn, *imvn, *mvh;    // moving strip: s, 1/s at local rows (B); halves (B+1)
+    const double2 *mdn, *imdn, *mdh;    // middle strip: (2B-1); halves (2B)
+    const double* ic2;                  // 1/c^2 on the grid (n*n)
+};
+
+// One subproblem strip for the factorisation kernel.
+struct SubDev {
+    int32_t prob;       // index into the ProbDev table
+    int32_t kind;       // SubKind
+    int32_t j0, dir;    // physical row (1-based) of local row 0, and +1/-1 going up the local rows
+    int64_t fac_off;    // offset of this strip's factor (in complex elements)
+};
+
+// One sweep chain: a front of one problem and a group of right-hand sides.
+struct ChainDev {
+    int32_t prob;
+    int32_t front;      // 0: upward front (F, B+1, ..., c-1); 1: downward front (E, n-B, ..., c+1)
+    int32_t rhs0, nq;   // first right-hand side and count (<= lanes / padded rows)
+    int64_t spill_off;  // offset of this chain's workspace (complex elements)
+};
+
+// Per-problem vector pointers for one application of the sweep (or one matvec).
+struct IoDev {
+    const void* in;
+    void* out;
+    const void* fac;    // factor store of the problem (complex elements of the factor precision)
+};
+
+__host__ __device__ constexpr int packed_size(int bs) { return bs * (bs + 1) / 2; }
+// index of (r, k), r <= k, in the row-major packed upper triangle of a bs x bs block
+__host__ __device__ constexpr int packed_index(int bs, int r, int k) { return r * bs - (r * (r - 1)) / 2 + (k - r); }
+
+// Profile of local row r of a strip: s2, 1/s2 at the row and s2 at the half rows below / above it.
+__device__ __forceinline__ void strip_profile(const ProbDev& P, int kind, int j0, int dir, int r,
+                                              double2& s2, double2& is2, double2& s2lo, double2& s2hi) {
+    if (kind == SUB_PHYS) {
+        int j = j0 + dir * r;
+        s2 = P.s2n[j - 1];
+        is2 = P.is2n[j - 1];
+        if (dir > 0) { s2lo = P.s2h[j - 1]; s2hi = P.s2h[j]; }
+        else         { s2lo = P.s2h[j];     s2hi = P.s2h[j - 1]; }
+    } else if (kind == SUB_MOVE) {
+        s2 = P.mvn[r]; is2 = P.imvn[r]; s2lo = P.mvh[r]; s2hi = P.mvh[r + 1];
+    } else {
+        s2 = P.mdn[r]; is2 = P.imdn[r]; s2lo = P.mdh[r]; s2hi = P.mdh[r + 1];
+    }
+}
+
+}  // namespace hs

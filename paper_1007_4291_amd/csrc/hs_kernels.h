@@ -1,0 +1,116 @@
+// Launchers of the helmsweep kernels (host side).  Every launcher enqueues on the given stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hs_common.h"
+
+namespace hs {
+
+// Offsets (in double2 elements) of the profile tables inside one problem's table block.
+struct ProfileLayout {
+    int32_t n, B;
+    int32_t s1n, is1n, s1h, s2n, is2n, s2h, mvn, imvn, mvh, mdn, imdn, mdh, total;
+    static ProfileLayout make(int n, int B) {
+        ProfileLayout L{};
+        L.n = n; L.B = B;
+        int o = 0;
+        L.s1n = o; o += n; L.is1n = o; o += n; L.s1h = o; o += n + 1;
+        L.s2n = o; o += n; L.is2n = o; o += n; L.s2h = o; o += n + 1;
+        L.mvn = o; o += B; L.imvn = o; o += B; L.mvh = o; o += B + 1;
+        L.mdn = o; o += 2 * B - 1; L.imdn = o; o += 2 * B - 1; L.mdh = o; o += 2 * B;
+        L.total = o;
+        return L;
+    }
+};
+
+// Operands of one problem's matvec: y = A x (f == nullptr) or y = f - A x.
+struct MvDev {
+    const void* x;   // complex128 or complex64 [nrhs][N]
+    void* y;         // complex128 [nrhs][N]
+    const void* f;   // complex128 [nrhs][N] or nullptr
+    int32_t nrhs;
+    int32_t pad;
+};
+
+void launch_profiles(const ProfileLayout& L, double2* tab, double h, double omega, double eta_p,
+                     double eta_m, double C, hipStream_t s);
+void launch_inv_c2(const double* c, double* ic2, int64_t N, int* bad, hipStream_t s);
+// Batched (io, blk_start device tables over nprob problems) or single problem (io == nullptr,
+// blk_start == nullptr: operands io_val, problem probs[0]).
+void launch_matvec(const ProbDev* probs, const MvDev* io, MvDev io_val, const int32_t* blk_start, int nprob,
+                   int total_blocks, int x_prec, hipStream_t s);
+int matvec_blocks(int n);
+
+// a2: factor `nsub` strips of height `bs` (all of one problem). prec 0: complex128 store,
+// 1: complex64 store.  status: device int, bit 0 set on a zero / non-finite pivot.
+// Returns false if `bs` has no compiled instance.
+bool launch_factor(int bs, int prec, const ProbDev* prob, const SubDev* subs, int nsub, int n,
+                   void* fac, int* status, hipStream_t s);
+
+// a3/a4: sweep chains and middle layer.
+//   phase 0: forward substitution + diagonal applications along each chain
+//   phase 1: backward substitution along each chain
+// vec_in/vec_out precisions: 0 complex128, 1 complex64.  Factor precision `prec`.
+// io: device table indexed by ChainDev::prob, or nullptr to use io_val for every chain.
+bool launch_chains(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
+                   const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s);
+bool launch_middle(int B, int prec, int in_prec, int out_prec, const ProbDev* probs,
+                   const ChainDev* mids, int nmids, const IoDev* io, IoDev io_val, void* spill, hipStream_t s);
+// Lanes per row group (right-hand sides per wave) for chains of strip height B and for the middle.
+int chain_rhs_per_wave(int B);
+int middle_rhs_per_wave(int B);
+// Padded rows per right-hand side inside a wave (the spill workspace is n * 64 complex per chain).
+int chain_padded_rows(int B);
+
+// Test hook: full-input / full-output solve of one strip (complex128 vectors [nrhs][rows][n]).
+bool launch_subsolve(int bs, int prec, const ProbDev* prob, const void* fac, int kind, int j0,
+                     int dir, const void* g, void* x, int nrhs, void* spill, hipStream_t s);
+
+// ---- FGMRES building blocks (a6), batched over systems --------------------------------------
+// A "system" is one right-hand side of one problem.  Vectors of system s start at base[s] and have
+// len[s] complex128 elements; tiles of KR_TILE elements, tile_start[s] = first tile of system s.
+struct SysVec {
+    double2* v;        // first Krylov vector V_0 of the system; V_j = v + j * vstride
+    void* z;           // first preconditioned vector Z_0 (complex128 or complex64); Z_j = z + j * zstride
+    double2* w;        // work vector
+    double2* x;        // solution
+    const double2* f;  // right-hand side
+    int64_t len, vstride, zstride;
+};
+
+constexpr int KR_TILE = 1024;
+constexpr int KR_THREADS = 256;
+
+// All tile kernels skip the tiles of systems with active[s] == 0 (active may be nullptr: all active).
+// partial[t * stride + i] = sum over tile t of conj(V_i) . w   for i = 0..j
+void launch_multidot(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j,
+                     double2* partial, int stride, const int32_t* active, hipStream_t s);
+// h[s * hstride + i] (+)= sum of partial over the tiles of system s, i < cnt
+void launch_reduce_partials(const int32_t* tile_start, int nsys, const double2* partial, int stride, int cnt,
+                            double2* h, int hstride, int accumulate, hipStream_t s);
+// w -= sum_{i<=j} h[s][i] V_i
+void launch_multiaxpy(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j,
+                      const double2* h, int hstride, const int32_t* active, hipStream_t s);
+// V_dst = w * scale[s]
+void launch_scale_to_v(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int dst,
+                       const double* scale, const int32_t* active, hipStream_t s);
+// x += sum_{i<cnt[s]} y[s][i] Z_i ; zprec 0 (complex128 Z) / 1 (complex64 Z)
+void launch_update_x(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, const int32_t* cnt,
+                     const double2* y, int ystride, int zprec, hipStream_t s);
+// ||vec|| per system, vec = w (which 0) or f (which 1); partial needs ntiles entries
+void launch_norms(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int which,
+                  double2* partial, double* out, const int32_t* active, hipStream_t s);
+// Column j of the Hessenberg matrix H[s][j][0..k] of every active system: set H[j+1][j] = nrm[s],
+// apply the previous Givens rotations, form the new one, rotate g; est[s] = |g[j+1]|,
+// inv_norm[s] = 1/nrm[s] (0 if nrm == 0).
+void launch_arnoldi_finish(int nsys, int j, int k, double2* H, double2* cs, double2* g, const double* nrm,
+                           double* inv_norm, double* est, const int32_t* active, hipStream_t s);
+// y[s] = H[s]^{-1} g[s] (upper triangular, size cnt[s])
+void launch_backsolve(int nsys, int k, const double2* H, const double2* g, const int32_t* cnt, double2* y,
+                      hipStream_t s);
+// g[s] = (beta[s], 0, ..., 0), inv[s] = 1/beta[s] (0 if beta == 0)
+void launch_start_cycle(int nsys, const double* beta, double* inv, double2* g, int gstride, hipStream_t s);
+
+}  // namespace hs

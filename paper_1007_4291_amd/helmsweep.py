@@ -1,0 +1,320 @@
+"""Thin ctypes binding of libhelmsweep.so (C-ABI in include/helmsweep.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.  Tensors are torch
+CUDA (HIP) tensors; their data pointers and the current torch stream are handed to the C-ABI.
+Importing this module fails loudly if the library has not been built (``python -m
+paper_1007_4291_amd.build``); there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhelmsweep.so")
+
+HELM_OK = 0
+HELM_ENOTCONV = 1
+HELM_EINVAL = -1
+HELM_ENOMEM = -2
+HELM_EHIP = -3
+HELM_ESINGULAR = -4
+HELM_C128 = 0
+HELM_C64 = 1
+
+# every symbol the header declares
+EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_problem_n", "helm_matvec", "sweep_factor",
+           "sweep_factor_bytes", "sweep_apply", "sweep_subsolve", "sweep_num_subproblems", "sweep_subproblem_rows",
+           "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "helm_free", "sweep_free",
+           "helm_batch_free"]
+
+
+class HelmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"helmsweep error {code}: {msg}")
+        self.code = code
+
+
+class HelmParams(C.Structure):
+    _fields_ = [("n", C.c_int32), ("omega", C.c_double), ("alpha", C.c_double), ("pml_w", C.c_int32),
+                ("mpml_w", C.c_int32), ("pml_C", C.c_double), ("b_convention", C.c_int32)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1007_4291_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, f64 = C.c_void_p, C.c_int32, C.c_double
+    sig = {
+        "helm_version": (C.c_char_p, []),
+        "helm_last_error": (C.c_char_p, []),
+        "helm_assemble": (C.c_int, [C.POINTER(HelmParams), vp, vp, C.POINTER(vp)]),
+        "helm_problem_n": (C.c_int, [vp]),
+        "helm_matvec": (C.c_int, [vp, vp, i32, vp, i32, vp]),
+        "sweep_factor": (C.c_int, [vp, i32, vp, C.POINTER(vp)]),
+        "sweep_factor_bytes": (C.c_int64, [vp]),
+        "sweep_apply": (C.c_int, [vp, vp, vp, i32, i32, vp]),
+        "sweep_subsolve": (C.c_int, [vp, i32, vp, vp, i32, vp]),
+        "sweep_num_subproblems": (C.c_int, [vp]),
+        "sweep_subproblem_rows": (C.c_int, [vp, i32]),
+        "fgmres_solve": (C.c_int, [vp, vp, vp, vp, i32, i32, f64, i32, C.POINTER(i32), C.POINTER(f64), vp]),
+        "helm_batch_create": (C.c_int, [C.POINTER(vp), C.POINTER(vp), C.POINTER(i32), i32, i32, vp, C.POINTER(vp)]),
+        "fgmres_solve_batch": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), f64, i32, C.POINTER(i32), C.POINTER(f64), vp]),
+        "sweep_apply_batch": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), vp]),
+        "helm_free": (None, [vp]),
+        "sweep_free": (None, [vp]),
+        "helm_batch_free": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> C.CDLL:
+    return _lib
+
+
+def version() -> str:
+    return _lib.helm_version().decode()
+
+
+def _check(rc: int, allow_notconv: bool = False) -> int:
+    if rc == HELM_OK or (allow_notconv and rc == HELM_ENOTCONV):
+        return rc
+    raise HelmError(rc, _lib.helm_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _prec_of(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return HELM_C128
+    if t.dtype == torch.complex64:
+        return HELM_C64
+    raise TypeError(f"expected complex128 or complex64 tensor, got {t.dtype}")
+
+
+def _check_vec(t, N: int, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() % N != 0:
+        raise ValueError(f"{name} has {t.numel()} elements, not a multiple of N={N}")
+
+
+@dataclass
+class Params:
+    n: int
+    omega: float
+    alpha: float = 2.0
+    pml_w: int = 12
+    mpml_w: int = 12
+    C: float = 20.0
+    b_convention: int = 0
+
+    def c_struct(self) -> HelmParams:
+        return HelmParams(self.n, self.omega, self.alpha, self.pml_w, self.mpml_w, self.C, self.b_convention)
+
+    @property
+    def B(self) -> int:
+        return self.mpml_w + 1 if self.b_convention == 0 else self.mpml_w
+
+
+class Problem:
+    """helm_problem_t: the assembled operator (a1)."""
+
+    def __init__(self, params: Params, c, stream=None):
+        torch = _torch()
+        self.params = params
+        self.n = params.n
+        self.N = params.n * params.n
+        c = c if isinstance(c, torch.Tensor) else torch.as_tensor(c)
+        c = c.to(device="cuda", dtype=torch.float64).contiguous()
+        if c.numel() != self.N:
+            raise ValueError(f"c has {c.numel()} values, expected n*n = {self.N}")
+        h = C.c_void_p()
+        p = params.c_struct()
+        _check(_lib.helm_assemble(C.byref(p), C.c_void_p(c.data_ptr()), C.c_void_p(_stream(stream)), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def matvec(self, x, y=None, stream=None):
+        """y = A x (FP64, eq. helmd); x complex128 or complex64 [nrhs, N] or [N]."""
+        torch = _torch()
+        _check_vec(x, self.N, "x")
+        nrhs = x.numel() // self.N
+        if y is None:
+            y = torch.empty(x.shape, dtype=torch.complex128, device=x.device)
+        _check_vec(y, self.N, "y")
+        if y.dtype != torch.complex128 or y.numel() != x.numel():
+            raise ValueError("y must be complex128 with the shape of x")
+        _check(_lib.helm_matvec(self._h, C.c_void_p(x.data_ptr()), _prec_of(x), C.c_void_p(y.data_ptr()), nrhs,
+                                C.c_void_p(_stream(stream))))
+        return y
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.helm_free(h)
+            self._h = None
+
+
+class Factors:
+    """sweep_factors_t: factored moving-PML subproblems (a2)."""
+
+    def __init__(self, A: Problem, prec: int = HELM_C128, stream=None):
+        self.A = A
+        self.prec = prec
+        h = C.c_void_p()
+        _check(_lib.sweep_factor(A.handle, prec, C.c_void_p(_stream(stream)), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def nbytes(self) -> int:
+        return int(_lib.sweep_factor_bytes(self._h))
+
+    @property
+    def num_subproblems(self) -> int:
+        return int(_lib.sweep_num_subproblems(self._h))
+
+    def subproblem_rows(self, sub: int) -> int:
+        return int(_lib.sweep_subproblem_rows(self._h, sub))
+
+    def apply(self, f, u=None, stream=None):
+        """u = M_alpha f (a3/a4); f, u complex128 or complex64 [nrhs, N]."""
+        torch = _torch()
+        _check_vec(f, self.A.N, "f")
+        if u is None:
+            u = torch.empty_like(f)
+        _check_vec(u, self.A.N, "u")
+        if u.dtype != f.dtype or u.numel() != f.numel():
+            raise ValueError("u must match f in dtype and size")
+        _check(_lib.sweep_apply(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), f.numel() // self.A.N,
+                                _prec_of(f), C.c_void_p(_stream(stream))))
+        return u
+
+    def subsolve(self, sub: int, g, x=None, stream=None):
+        """Solve one strip with full input/output: g, x complex128 [nrhs, rows, n]."""
+        torch = _torch()
+        rows = self.subproblem_rows(sub)
+        if rows < 0:
+            raise ValueError("subproblem index out of range")
+        if g.dtype != torch.complex128 or not g.is_contiguous() or g.numel() % (rows * self.A.n):
+            raise ValueError("g must be contiguous complex128 [nrhs, rows, n]")
+        if x is None:
+            x = torch.empty_like(g)
+        nrhs = g.numel() // (rows * self.A.n)
+        _check(_lib.sweep_subsolve(self._h, sub, C.c_void_p(g.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
+                                   C.c_void_p(_stream(stream))))
+        return x
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.sweep_free(h)
+            self._h = None
+
+
+@dataclass
+class SolveResult:
+    u: object
+    iters: List[int]
+    relres: List[float]
+    converged: bool
+
+
+def fgmres(A: Problem, M: Factors, f, u=None, restart: int = 20, tol: float = 1e-6, maxit: int = 1000,
+           stream=None) -> SolveResult:
+    """Right-preconditioned FGMRES(restart) (a6); f complex128 [nrhs, N]; u = x0 in / solution out."""
+    torch = _torch()
+    _check_vec(f, A.N, "f")
+    if f.dtype != torch.complex128:
+        raise ValueError("f must be complex128")
+    if u is None:
+        u = torch.zeros_like(f)
+    _check_vec(u, A.N, "u")
+    nrhs = f.numel() // A.N
+    it = (C.c_int32 * nrhs)()
+    rr = (C.c_double * nrhs)()
+    rc = _lib.fgmres_solve(A.handle, M.handle, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), nrhs, restart,
+                           tol, maxit, it, rr, C.c_void_p(_stream(stream)))
+    _check(rc, allow_notconv=True)
+    return SolveResult(u, list(it), list(rr), rc == HELM_OK)
+
+
+class Batch:
+    """helm_batch_t: many problems of uneven size solved together (a7)."""
+
+    def __init__(self, problems: Sequence[Problem], factors: Sequence[Factors], nrhs: Sequence[int],
+                 restart: int = 20, stream=None):
+        cnt = len(problems)
+        self.problems, self.factors, self.nrhs = list(problems), list(factors), [int(r) for r in nrhs]
+        self.restart = restart
+        Ah = (C.c_void_p * cnt)(*[p.handle.value for p in problems])
+        Mh = (C.c_void_p * cnt)(*[m.handle.value for m in factors])
+        R = (C.c_int32 * cnt)(*self.nrhs)
+        h = C.c_void_p()
+        _check(_lib.helm_batch_create(Ah, Mh, R, cnt, restart, C.c_void_p(_stream(stream)), C.byref(h)))
+        self._h = h
+
+    def _ptrs(self, ts, name, dtype_ok):
+        if len(ts) != len(self.problems):
+            raise ValueError(f"{name}: expected {len(self.problems)} tensors")
+        for t, p, r in zip(ts, self.problems, self.nrhs):
+            _check_vec(t, p.N, name)
+            if t.numel() != r * p.N or not dtype_ok(t):
+                raise ValueError(f"{name}: wrong size or dtype")
+        return (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def solve(self, f: Sequence, u: Optional[Sequence] = None, tol: float = 1e-6, maxit: int = 1000, stream=None):
+        torch = _torch()
+        if u is None:
+            u = [torch.zeros_like(t) for t in f]
+        c128 = lambda t: t.dtype == torch.complex128
+        fp, up = self._ptrs(f, "f", c128), self._ptrs(u, "u", c128)
+        tot = sum(self.nrhs)
+        it = (C.c_int32 * tot)()
+        rr = (C.c_double * tot)()
+        rc = _lib.fgmres_solve_batch(self._h, fp, up, tol, maxit, it, rr, C.c_void_p(_stream(stream)))
+        _check(rc, allow_notconv=True)
+        return SolveResult(u, list(it), list(rr), rc == HELM_OK)
+
+    def apply(self, f: Sequence, u: Optional[Sequence] = None, stream=None):
+        torch = _torch()
+        if u is None:
+            u = [torch.empty_like(t) for t in f]
+        c128 = lambda t: t.dtype == torch.complex128
+        _check(_lib.sweep_apply_batch(self._h, self._ptrs(f, "f", c128), self._ptrs(u, "u", c128),
+                                      C.c_void_p(_stream(stream))))
+        return u
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.helm_batch_free(h)
+            self._h = None

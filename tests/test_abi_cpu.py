@@ -1,0 +1,74 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects bad arguments before
+touching the device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "helmsweep.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def hs():
+    from paper_1007_4291_amd import helmsweep
+    return helmsweep
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared()
+    for req in ["helm_assemble", "sweep_factor", "sweep_apply", "helm_matvec", "fgmres_solve",
+                "helm_batch_create", "fgmres_solve_batch"]:
+        assert req in names
+
+
+def test_library_exports_every_declared_symbol(hs):
+    lib = C.CDLL(hs.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(hs.EXPORTS) == _declared()
+    assert "gfx950" in hs.version()
+
+
+def _params(hs, **kw):
+    d = dict(n=63, omega=50.0, alpha=2.0, pml_w=8, mpml_w=8, pml_C=20.0, b_convention=0)
+    d.update(kw)
+    return hs.HelmParams(**d)
+
+
+@pytest.mark.parametrize("bad", [dict(n=20), dict(omega=0.0), dict(omega=float("nan")), dict(alpha=-1.0),
+                                 dict(pml_w=0), dict(mpml_w=0), dict(mpml_w=5), dict(pml_C=0.0),
+                                 dict(b_convention=2), dict(pml_w=40), dict(n=40000)])
+def test_assemble_rejects_bad_params(hs, bad):
+    """Parameter checks run before any device call and return HELM_EINVAL with a message."""
+    p = _params(hs, **bad)
+    h = C.c_void_p()
+    rc = hs.lib().helm_assemble(C.byref(p), C.c_void_p(1), None, C.byref(h))
+    assert rc == hs.HELM_EINVAL
+    assert len(hs.lib().helm_last_error()) > 0
+    assert not h.value
+
+
+def test_null_handles_rejected(hs):
+    L = hs.lib()
+    assert L.helm_assemble(None, None, None, None) == hs.HELM_EINVAL
+    assert L.helm_matvec(None, None, 0, None, 1, None) == hs.HELM_EINVAL
+    assert L.sweep_factor(None, 0, None, None) == hs.HELM_EINVAL
+    assert L.sweep_apply(None, None, None, 1, 0, None) == hs.HELM_EINVAL
+    assert L.fgmres_solve(None, None, None, None, 1, 20, 1e-6, 10, None, None, None) == hs.HELM_EINVAL
+    assert L.helm_batch_create(None, None, None, 0, 20, None, None) == hs.HELM_EINVAL
+    assert L.fgmres_solve_batch(None, None, None, 1e-6, 10, None, None, None) == hs.HELM_EINVAL
+    assert L.helm_problem_n(None) == -1
+    assert L.sweep_factor_bytes(None) == 0
+    assert L.sweep_num_subproblems(None) == -1
+    L.helm_free(None)
+    L.sweep_free(None)
+    L.helm_batch_free(None)

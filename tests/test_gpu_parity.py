@@ -1,0 +1,264 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle, element by element.
+
+Tolerances: FP64 path 1e-14 (matvec, a sum of five products) / 1e-11 (one strip solve) / 1e-10
+(the whole sweep: ~2n strip solves in sequence); complex64 factors and sweep 2e-5 per strip and
+1e-4 for the sweep (single-precision rounding through n-column recurrences); FGMRES: the solution
+agrees with the oracle's to 1e-6 relative (both stop at 1e-6 true residual, same Krylov sequence).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import helmholtz as OH
+from oracle import krylov as OK
+from oracle import sweep as OS
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hs():
+    from paper_1007_4291_amd import helmsweep
+    return helmsweep
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    return torch
+
+
+def _case(name):
+    """(oracle params, c, gpu params) for small parity cases."""
+    if name == "cfg1":
+        pr = workloads.cfg1()
+        c, n, om, w = pr.c, pr.n, pr.omega, 8
+        pw = w
+    elif name == "grf45":
+        n, om, w, pw = 45, 2 * math.pi * 5, 4, 4
+        c = workloads.velocity_grf(n, seed=77)
+    elif name == "even40":
+        n, om, w, pw = 40, 2 * math.pi * 4, 3, 6
+        c = workloads.velocity_lens(n)
+    elif name == "lens61w12":
+        n, om, w, pw = 61, 2 * math.pi * 6, 12, 12
+        c = workloads.velocity_lens(n)
+    elif name == "wg71w16":
+        n, om, w, pw = 71, 2 * math.pi * 7, 16, 16
+        c = workloads.velocity_waveguide(n, seed=5)
+    else:
+        raise KeyError(name)
+    op = OH.Params(n=n, omega=om, alpha=2.0, pml_w=pw, mpml_w=w)
+    return op, c
+
+
+def _gpu_problem(hs, torch, op, c):
+    gp = hs.Params(n=op.n, omega=op.omega, alpha=op.alpha, pml_w=op.pml_w, mpml_w=op.mpml_w, C=op.C)
+    return hs.Problem(gp, torch.as_tensor(c, dtype=torch.float64, device="cuda"))
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "even40", "wg71w16"])
+def test_matvec_parity(hs, torch, name):
+    op, c = _case(name)
+    _log("matvec", name)
+    A = _gpu_problem(hs, torch, op, c)
+    Ao = OH.assemble(op, c)
+    x = workloads.random_rhs(op.n, 3, seed=1)
+    y = A.matvec(torch.as_tensor(x, device="cuda")).cpu().numpy()
+    for k in range(3):
+        assert _rel(y[k], Ao @ x[k]) <= 1e-14
+    x32 = torch.as_tensor(x, device="cuda").to(torch.complex64)
+    y32 = A.matvec(x32).cpu().numpy()
+    xr = x32.cpu().numpy().astype(np.complex128)
+    for k in range(3):
+        assert _rel(y32[k], Ao @ xr[k]) <= 1e-14
+
+
+def _sub_map(op, M, sub):
+    """GPU strip index -> (oracle BandLU, local->oracle row permutation)."""
+    L_lo = op.mid - 1 - op.B
+    if sub == 0:
+        return M.F, None
+    if sub <= L_lo:
+        return M.lower[sub - 1], None
+    if sub == L_lo + 1:
+        return M.E, "flip"
+    nsub = len(M.lower) + len(M.upper) + 3
+    if sub == nsub - 1:
+        return M.mid, None
+    return M.upper[sub - L_lo - 2], "flip"
+
+
+@pytest.mark.parametrize("name,prec", [("cfg1", 0), ("grf45", 0), ("even40", 0), ("wg71w16", 0),
+                                       ("cfg1", 1), ("lens61w12", 1)])
+def test_strip_solve_parity(hs, torch, name, prec):
+    """Each strip's block LU solve (a2 factor + one solve) equals the oracle's LAPACK band solve."""
+    op, c = _case(name)
+    _log("strip", name, prec)
+    A = _gpu_problem(hs, torch, op, c)
+    F = hs.Factors(A, prec)
+    Mo = OS.factor(op, c)
+    nsub = F.num_subproblems
+    assert nsub == len(Mo.lower) + len(Mo.upper) + 3
+    L_lo = op.mid - 1 - op.B
+    picks = sorted(set([0, 1, L_lo, L_lo + 1, L_lo + 2, nsub - 2, nsub - 1]))
+    tol = 1e-11 if prec == 0 else 2e-5
+    rng = np.random.default_rng(3)
+    for sub in picks:
+        band, flip = _sub_map(op, Mo, sub)
+        R = F.subproblem_rows(sub)
+        assert R == band.R
+        g = rng.standard_normal((5, R, op.n)) + 1j * rng.standard_normal((5, R, op.n))
+        x = F.subsolve(sub, torch.as_tensor(g, device="cuda")).cpu().numpy()
+        go = g[:, ::-1, :] if flip else g
+        xo = band.solve_rows(np.ascontiguousarray(np.transpose(go, (1, 2, 0))))
+        xo = np.transpose(xo, (2, 0, 1))
+        if flip:
+            xo = xo[:, ::-1, :]
+        err = _rel(x, xo)
+        _log(f"  sub {sub} rows {R}: rel {err:.2e}")
+        assert err <= tol
+
+
+@pytest.mark.parametrize("name,nrhs", [("cfg1", 1), ("cfg1", 5), ("grf45", 2), ("even40", 3), ("wg71w16", 2),
+                                       ("lens61w12", 1)])
+def test_sweep_apply_parity_c128(hs, torch, name, nrhs):
+    op, c = _case(name)
+    _log("apply c128", name, nrhs)
+    A = _gpu_problem(hs, torch, op, c)
+    F = hs.Factors(A, hs.HELM_C128)
+    Mo = OS.factor(op, c)
+    f = workloads.random_rhs(op.n, nrhs, seed=11)
+    u = F.apply(torch.as_tensor(f, device="cuda")).cpu().numpy()
+    uo = OS.apply_sweep(Mo, f)
+    err = _rel(u, uo)
+    _log(f"  rel {err:.2e}")
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["cfg1", "lens61w12"])
+def test_sweep_apply_parity_c64(hs, torch, name):
+    op, c = _case(name)
+    _log("apply c64", name)
+    A = _gpu_problem(hs, torch, op, c)
+    F = hs.Factors(A, hs.HELM_C64)
+    Mo = OS.factor(op, c)
+    f = workloads.random_rhs(op.n, 3, seed=12)
+    u = F.apply(torch.as_tensor(f, device="cuda").to(torch.complex64)).cpu().numpy()
+    uo = OS.apply_sweep(Mo, f.astype(np.complex64).astype(np.complex128))
+    err = _rel(u.astype(np.complex128), uo)
+    _log(f"  rel {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_gpu_preconditioner_symmetric(hs, torch):
+    """x^t M y = y^t M x on the GPU path (complex symmetric LDL^t)."""
+    op, c = _case("grf45")
+    A = _gpu_problem(hs, torch, op, c)
+    F = hs.Factors(A, hs.HELM_C128)
+    x, y = workloads.random_rhs(op.n, 2, seed=21)
+    My = F.apply(torch.as_tensor(y[None], device="cuda")).cpu().numpy()[0]
+    Mx = F.apply(torch.as_tensor(x[None], device="cuda")).cpu().numpy()[0]
+    a, b = x @ My, y @ Mx
+    assert abs(a - b) <= 1e-11 * abs(a)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fgmres_cfg1_parity(hs, torch, prec):
+    pr = workloads.cfg1()
+    op = OH.Params(n=pr.n, omega=pr.omega, pml_w=pr.pml_w, mpml_w=pr.mpml_w)
+    _log("fgmres cfg1 prec", prec)
+    A = _gpu_problem(hs, torch, op, pr.c)
+    F = hs.Factors(A, prec)
+    res = hs.fgmres(A, F, torch.as_tensor(pr.f, device="cuda"), restart=20, tol=1e-6)
+    u = res.u.cpu().numpy()[0]
+    Ao = OH.assemble(op, pr.c)
+    Mo = OS.factor(op, pr.c)
+    ro = OK.fgmres(lambda v: Ao @ v, lambda v: OS.apply_sweep(Mo, v), pr.f[0], 20, 1e-6)
+    true_rel = np.linalg.norm(pr.f[0] - Ao @ u) / np.linalg.norm(pr.f[0])
+    err = _rel(u, ro.x)
+    _log(f"  iters gpu {res.iters} oracle {ro.iters}; true relres {true_rel:.2e}; err vs oracle {err:.2e}")
+    assert res.converged
+    assert true_rel <= 1e-6
+    assert abs(res.relres[0] - true_rel) <= 1e-9
+    if prec == 0:
+        assert abs(res.iters[0] - ro.iters) <= 1
+        assert err <= 1e-6
+    else:
+        assert res.iters[0] <= ro.iters + 3
+        assert err <= 1e-4
+
+
+def test_fgmres_cfg2_fp64_parity(hs, torch):
+    """Config 2 (n = 255, lens, Gaussian source, widths 12) in FP64 against the oracle."""
+    pr = workloads.cfg2()
+    op = OH.Params(n=pr.n, omega=pr.omega, pml_w=pr.pml_w, mpml_w=pr.mpml_w)
+    _log("fgmres cfg2")
+    A = _gpu_problem(hs, torch, op, pr.c)
+    F = hs.Factors(A, hs.HELM_C128)
+    res = hs.fgmres(A, F, torch.as_tensor(pr.f, device="cuda"), restart=20, tol=1e-6)
+    u = res.u.cpu().numpy()[0]
+    Ao = OH.assemble(op, pr.c)
+    Mo = OS.factor(op, pr.c)
+    ro = OK.fgmres(lambda v: Ao @ v, lambda v: OS.apply_sweep(Mo, v), pr.f[0], 20, 1e-6)
+    err = _rel(u, ro.x)
+    true_rel = np.linalg.norm(pr.f[0] - Ao @ u) / np.linalg.norm(pr.f[0])
+    _log(f"  iters gpu {res.iters} oracle {ro.iters}; true relres {true_rel:.2e}; err {err:.2e}")
+    assert res.converged and true_rel <= 1e-6
+    assert abs(res.iters[0] - ro.iters) <= 1
+    assert err <= 1e-6
+
+
+def test_batch_equals_individual_solves(hs, torch):
+    """Uneven batch (three sizes, several right-hand sides) == per-problem solves."""
+    specs = [(47, 4, 3), (63, 4, 2), (31, 4, 1)]
+    probs, facs, fs, singles = [], [], [], []
+    for n, w, R in specs:
+        op = OH.Params(n=n, omega=2 * math.pi * n / 8, pml_w=w, mpml_w=w)
+        c = workloads.velocity_layered(n, seed=n)
+        A = _gpu_problem(hs, torch, op, c)
+        F = hs.Factors(A, hs.HELM_C128)
+        f = torch.as_tensor(workloads.random_rhs(n, R, seed=n + 1), device="cuda")
+        probs.append(A); facs.append(F); fs.append(f)
+        singles.append(hs.fgmres(A, F, f, restart=10, tol=1e-8))
+    b = hs.Batch(probs, facs, [s[2] for s in specs], restart=10)
+    res = b.solve(fs, tol=1e-8)
+    assert res.converged
+    k = 0
+    for s, u in zip(singles, res.u):
+        for q in range(len(s.iters)):
+            assert res.iters[k] == s.iters[q]
+            k += 1
+        assert _rel(u.cpu().numpy(), s.u.cpu().numpy()) <= 1e-12
+
+
+def test_error_paths_on_gpu(hs, torch):
+    op, c = _case("grf45")
+    c_bad = c.copy()
+    c_bad[100] = float("nan")
+    with pytest.raises(hs.HelmError) as ei:
+        _gpu_problem(hs, torch, op, c_bad)
+    assert ei.value.code == hs.HELM_EINVAL
+    c_neg = c.copy()
+    c_neg[7] = -1.0
+    with pytest.raises(hs.HelmError):
+        _gpu_problem(hs, torch, op, c_neg)
+    A = _gpu_problem(hs, torch, op, c)
+    F = hs.Factors(A, hs.HELM_C128)
+    f = torch.as_tensor(workloads.random_rhs(op.n, 1, seed=3), device="cuda")
+    res = hs.fgmres(A, F, f, restart=20, tol=1e-10, maxit=1)
+    assert not res.converged and res.iters == [1] and res.relres[0] > 1e-10
+    with pytest.raises(hs.HelmError):
+        hs.fgmres(A, F, f, tol=2.0)
