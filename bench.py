@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Throughput of the moving-PML sweeping preconditioner hot path on one MI355X.
+
+One step = one pass of the whole hot path over the workload: re-assemble every problem (a1),
+re-factor every moving-PML strip (a2), then solve every right-hand side of every problem to a true
+FP64 relative residual of 1e-6 with FGMRES (a3-a7: sweep forward/backward, FP64 matvec, FP64
+Arnoldi), all problems batched into one set of launches per phase.  Inputs are resident in HBM when
+the timed region starts.
+
+Metric: preconditioned solves/sec, reported as RHS*N unknowns/s (right-hand sides times unknowns
+per problem, per second), FP32-factor batched form vs the plain FP64 form on the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|lens255|grf1023|const63]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched", choices=["batched", "lens255", "grf1023", "const63"])
+    ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 comparison (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-size", type=int, default=32, help="problems per size in the batched workload")
+    return ap.parse_args()
+
+
+def build_workload(name: str, per_size: int):
+    import workloads as W
+    if name == "batched":
+        probs = W.cfg4(per_size=per_size)
+        desc = (f"batched uneven: {len(probs)} problems, n in {{127,255,511}} x {per_size}, omega/2pi = n/8, "
+                f"layered velocity (5-10 layers, c in [0.8,1.5]), 8 point sources each, PML and moving-PML "
+                f"width 12 (B=13), FGMRES(20) to 1e-6")
+    elif name == "lens255":
+        probs = [W.cfg2()]
+        desc = "n=255, omega/2pi=32, converging lens, Gaussian source, widths 12, FGMRES(20) to 1e-6"
+    elif name == "grf1023":
+        probs = [W.cfg3()]
+        desc = "n=1023, omega/2pi=128, Gaussian random velocity, Gaussian source, widths 12, FGMRES(20) to 1e-6"
+    else:
+        probs = [W.cfg1()]
+        desc = "n=63, omega/2pi=8, c=1, point source, widths 8, FGMRES(20) to 1e-6"
+    return probs, desc
+
+
+class Runner:
+    """Device-resident problems, factors and one batch for a given factor precision."""
+
+    def __init__(self, hs, torch, probs, prec):
+        self.hs, self.torch = hs, torch
+        self.c = [torch.as_tensor(p.c, dtype=torch.float64, device="cuda") for p in probs]
+        self.f = [torch.as_tensor(p.f, dtype=torch.complex128, device="cuda").contiguous() for p in probs]
+        self.u = [torch.zeros_like(f) for f in self.f]
+        self.A = [hs.Problem(hs.Params(n=p.n, omega=p.omega, alpha=p.alpha, pml_w=p.pml_w, mpml_w=p.mpml_w), c)
+                  for p, c in zip(probs, self.c)]
+        self.M = [hs.Factors(A, prec) for A in self.A]
+        restart = probs[0].restart
+        self.batch = hs.Batch(self.A, self.M, [p.nrhs for p in probs], restart=restart)
+        self.tol = probs[0].tol
+        self.last = None
+
+    def step(self):
+        for A, c in zip(self.A, self.c):
+            A.reassemble(c)
+        for M in self.M:
+            M.refactor()
+        for u in self.u:
+            u.zero_()
+        self.last = self.batch.solve(self.f, self.u, tol=self.tol, maxit=400)
+        return self.last
+
+
+def timed(runner, torch, steps, warmup):
+    for _ in range(warmup):
+        runner.step()
+    runner.hs.timing_read(reset=True)
+    runner.hs.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = runner.step()
+        if not res.converged:
+            raise RuntimeError("a system did not reach the tolerance")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    runner.hs.timing_enable(False)
+    phases = runner.hs.timing_read(reset=True)
+    return (t1 - t0) / steps, phases
+
+
+def sweep_bytes_flops(probs, B, fac_bytes, vin, vout):
+    """Algorithmic HBM bytes and flops of one forward-chain and one backward-chain launch.
+
+    Factor: every B-row strip of both fronts is read twice per phase (the column-forward and the
+    column-backward pass of its block LU solve), n columns of B(B+1)/2 packed complex entries,
+    once per problem whatever the grouping of right-hand sides.  Vectors: per right-hand side, the
+    forward phase reads the input row and the neighbour's output row and writes the output row of
+    every moving layer, plus all rows of F and E; the backward phase reads the neighbour and own
+    output rows and writes the own row.  Flops: 2 passes x n columns x B^2 complex MACs (8 flops)
+    per strip per right-hand side.
+    """
+    pack = B * (B + 1) // 2
+    b0 = b1 = fl = 0
+    for p in probs:
+        n, R = p.n, p.nrhs
+        c = (n + 1) // 2 if n % 2 else n // 2 + 1
+        L = (c - 1 - B) + (n - B - c)
+        strips = L + 2
+        fac = strips * 2 * n * pack * fac_bytes
+        b0 += fac + R * n * (2 * B * (vin + vout) + L * (vin + 2 * vout))
+        b1 += fac + R * n * (L * 3 * vout + 2 * (1 + 2 * B) * vout)
+        fl += R * strips * 2 * n * B * B * 8
+    return b0, b1, fl
+
+
+def cpu_baseline(probs):
+    """The oracle, untuned, on a bounded sample: one problem of the workload, all its right-hand sides."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import helmholtz as OH
+    from oracle import krylov as OK
+    from oracle import sweep as OS
+    p = min(probs, key=lambda q: q.n)
+    op = OH.Params(n=p.n, omega=p.omega, alpha=p.alpha, pml_w=p.pml_w, mpml_w=p.mpml_w)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        Ao = OH.assemble(op, p.c)
+        Mo = OS.factor(op, p.c)
+        sols = []
+        for q in range(p.nrhs):
+            r = OK.fgmres(lambda v: Ao @ v, lambda v: OS.apply_sweep(Mo, v), p.f[q], p.restart, p.tol)
+            sols.append(r.x)
+        t = time.perf_counter() - t0
+    return {"value": p.nrhs * p.N / t, "unit": "RHS*N unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 problem (n={p.n}, {p.nrhs} RHS, {p.name}): assemble + factor + FGMRES({p.restart}) to "
+                      f"{p.tol:g}, numpy/scipy FP64, 1 thread, {t:.1f} s"}, p, np.stack(sols)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print("bench.py: only the one-GPU configuration exists (no multi-GPU path in this build)", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    import paper_1007_4291_amd.helmsweep as hs
+
+    probs, desc = build_workload(a.workload, a.per_size)
+    prec = hs.HELM_C64 if a.prec == "c64" else hs.HELM_C128
+    B = probs[0].mpml_w + 1
+    tot_unknowns = sum(p.nrhs * p.N for p in probs)
+    nsys = sum(p.nrhs for p in probs)
+    print(f"[bench] workload {a.workload}: {len(probs)} problems, {nsys} systems, {tot_unknowns:.3e} RHS*N",
+          file=sys.stderr, flush=True)
+
+    run = Runner(hs, torch, probs, prec)
+    t_step, ph = timed(run, torch, a.steps, a.warmup)
+    res = run.last
+    print(f"[bench] {a.prec}: {t_step * 1e3:.1f} ms/step, iters {min(res.iters)}-{max(res.iters)}",
+          file=sys.stderr, flush=True)
+    value = tot_unknowns / t_step
+    u_main = [u.clone() for u in run.u]
+
+    # roofline of the dominant kernel: the sweep chain kernel (forward + backward launches)
+    fac_b = 8 if prec == hs.HELM_C64 else 16
+    b0, b1, fl = sweep_bytes_flops(probs, B, fac_b, 16, fac_b)
+    ms_f, n_f = ph["sweep_fwd"]
+    ms_b, n_b = ph["sweep_bwd"]
+    avg_ms = (ms_f + ms_b) / max(1, n_f + n_b)
+    bytes_per_launch = (b0 + b1) / 2
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "k_chain (sweep forward/backward chains)", "avg_launch_ms": round(avg_ms, 4),
+            "launches": n_f + n_b, "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            "tflops": round(fl / (avg_ms * 1e-3) / 1e12, 4)}
+
+    out = {"metric": "preconditioned solves/sec (RHS*N unknowns/s) at 1e-6 residual; FP32-batched vs FP64",
+           "value": value, "unit": "RHS*N unknowns/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": t_step * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": a.prec, "data": "synthetic",
+           "config": {"workload": desc, "problems": len(probs), "systems": nsys, "B": B,
+                      "restart": probs[0].restart, "tol": probs[0].tol,
+                      "factor_prec": a.prec, "krylov_prec": "f64"},
+           "solves_per_s": nsys / t_step,
+           "iters": {"min": min(res.iters), "max": max(res.iters), "mean": float(np.mean(res.iters))},
+           "max_true_relres": max(res.relres),
+           "phase_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in ph.items()},
+           "roofline": roof}
+
+    if a.fp64_steps > 0 and prec != hs.HELM_C128:
+        del run
+        torch.cuda.empty_cache()
+        run64 = Runner(hs, torch, probs, hs.HELM_C128)
+        t64, _ = timed(run64, torch, a.fp64_steps, 1)
+        err = max(float(torch.linalg.vector_norm(u1 - u2) / torch.linalg.vector_norm(u2))
+                  for u1, u2 in zip(u_main, run64.u))
+        out["fp64"] = {"value": tot_unknowns / t64, "ms_per_step": t64 * 1e3,
+                       "iters_max": max(run64.last.iters)}
+        out["speedup_vs_fp64"] = t64 / t_step
+        out["max_rel_err_vs_fp64_gpu"] = err
+        print(f"[bench] c128: {t64 * 1e3:.1f} ms/step; speedup {t64 / t_step:.2f}x; err {err:.2e}",
+              file=sys.stderr, flush=True)
+        del run64
+
+    if not a.no_cpu_baseline:
+        cb, p, xs = cpu_baseline(probs)
+        out["cpu_baseline"] = cb
+        k = [i for i, q in enumerate(probs) if q is p][0]
+        u_gpu = u_main[k].cpu().numpy()
+        out["max_rel_err_vs_oracle_sample"] = float(max(np.linalg.norm(u_gpu[q] - xs[q]) / np.linalg.norm(xs[q])
+                                                        for q in range(p.nrhs)))
+        print(f"[bench] cpu baseline {cb['value']:.3e} RHS*N/s", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

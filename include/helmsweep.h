@@ -81,6 +81,10 @@ const char* helm_last_error(void);
  * Supported strip heights: B and 2B-1 both in {4,5,7,9,13,17,25,33} (e.g. B = 4,5,7,9,13,17). */
 int helm_assemble(const helm_params* p, const double* c, void* stream, helm_problem_t* out);
 
+/* a1 again, in place: recompute the problem's tables from a new velocity c (same n and parameters)
+ * without allocating.  Same checks and synchronisation as helm_assemble. */
+int helm_reassemble(helm_problem_t A, const double* c, void* stream);
+
 /* Grid size of a problem (n) or -1 for a NULL handle. */
 int helm_problem_n(helm_problem_t A);
 
@@ -98,6 +102,10 @@ int helm_matvec(helm_problem_t A, const void* x, int32_t x_prec, void* y, int32_
  * symmetric Lambda_i^{-1} stored packed (upper triangle) in `prec`.
  * Returns HELM_ESINGULAR if a block has a zero or non-finite pivot.  Synchronises `stream`. */
 int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_factors_t* out);
+
+/* a2 again, in place: recompute every strip factor from the problem's current tables (after
+ * helm_reassemble) without allocating.  Same checks and synchronisation as sweep_factor. */
+int sweep_refactor(sweep_factors_t M, void* stream);
 
 /* Bytes of device memory held by a factor handle (0 for NULL). */
 int64_t sweep_factor_bytes(sweep_factors_t M);
@@ -146,6 +154,15 @@ int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* const* u, dou
 /* Apply M_alpha to every right-hand side of the batch in one set of launches (f[k], u[k] as above,
  * complex128). */
 int sweep_apply_batch(helm_batch_t b, const void* const* f, void* const* u, void* stream);
+
+/* Per-phase kernel timing with HIP events recorded on the launch stream around every kernel
+ * group (process-wide; off by default).  Phases: 0 assemble, 1 factor, 2 sweep forward chains,
+ * 3 sweep middle layer, 4 sweep backward chains, 5 matvec, 6 Krylov vector kernels.
+ * helm_timing_read fills ms[7] (summed milliseconds) and launches[7] (kernel launches), waiting
+ * for the recorded events; reset != 0 clears the records. */
+#define HELM_NPHASES 7
+int helm_timing_enable(int32_t on);
+int helm_timing_read(double* ms, int64_t* launches, int32_t reset);
 
 void helm_free(helm_problem_t A);
 void sweep_free(sweep_factors_t M);

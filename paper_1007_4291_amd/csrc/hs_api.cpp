@@ -76,6 +76,44 @@ bool supported_B(int B) { return B == 4 || B == 5 || B == 7 || B == 9 || B == 13
 
 constexpr int64_t kMaxN = 32767;
 
+// Per-phase kernel timing (process-wide, off by default): a start/stop event pair around each
+// kernel group, read back and summed on demand.
+enum Phase { PH_ASSEMBLE = 0, PH_FACTOR, PH_SWEEP_FWD, PH_SWEEP_MID, PH_SWEEP_BWD, PH_MATVEC, PH_KRYLOV, PH_N };
+struct TimerRec { int phase; int launches; hipEvent_t a, b; };
+struct Timing {
+    bool on = false;
+    std::vector<TimerRec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+        return e;
+    }
+};
+Timing& timing() { static Timing t; return t; }
+
+// Records an event pair around the enclosed launches when timing is on.
+struct PhaseScope {
+    TimerRec rec{};
+    hipStream_t s;
+    bool live = false;
+    PhaseScope(int phase, hipStream_t st, int launches = 1) : s(st) {
+        Timing& T = timing();
+        if (!T.on) return;
+        rec.phase = phase;
+        rec.launches = launches;
+        rec.a = T.get();
+        rec.b = T.get();
+        if (!rec.a || !rec.b) return;
+        live = hipEventRecord(rec.a, s) == hipSuccess;
+    }
+    ~PhaseScope() {
+        if (!live) return;
+        if (hipEventRecord(rec.b, s) == hipSuccess) timing().recs.push_back(rec);
+    }
+};
+
 }  // namespace
 
 struct helm_problem_s {
@@ -96,7 +134,7 @@ struct sweep_factors_s {
     std::vector<int> sub_rows;
     // single-problem chain tables (rebuilt when nrhs changes)
     DevBuf chains, mids;
-    int chains_nrhs = -1, nchains = 0, nmids = 0;
+    int chains_nrhs = -1, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1;
     helm_batch_t solo = nullptr;    // cached batch of one for fgmres_solve
     int solo_nrhs = -1, solo_restart = -1;
     ~sweep_factors_s();
@@ -108,7 +146,7 @@ struct helm_batch_s {
     std::vector<sweep_factors_t> M;
     std::vector<int> nrhs;
     std::vector<int64_t> N;
-    int nsys = 0, ntiles = 0, mv_blocks = 0, nchains = 0, nmids = 0;
+    int nsys = 0, ntiles = 0, mv_blocks = 0, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1;
     std::vector<int> sys_prob, sys_rhs;
     std::vector<int32_t> tiles_h;
     DevBuf probs, chains, mids, io_sweep, io_apply, mv_z, mv_res, mv_blk, sv, tiles;
@@ -143,6 +181,29 @@ static int check_params(const helm_params* p, int* Bout) {
     return HELM_OK;
 }
 
+// Run the a1 kernels into A's tables from velocity c and check c.
+static int assemble_into(helm_problem_t A, const double* c, hipStream_t s) {
+    const helm_params* p = &A->prm;
+    const int n = A->n, B = A->B;
+    const int64_t N = (int64_t)n * n;
+    HIPCHK(hipMemsetAsync(A->flag.p, 0, sizeof(int), s));
+    const double h = A->h;
+    const double eta_p = (p->b_convention == 0 ? p->pml_w + 1 : p->pml_w) * h;
+    const double eta_m = B * h;
+    {
+        PhaseScope ph(PH_ASSEMBLE, s, 2);
+        launch_profiles(A->lay, A->tab.as<double2>(), h, p->omega, eta_p, eta_m, p->pml_C, s);
+        LAUNCHCHK();
+        launch_inv_c2(c, A->ic2.as<double>(), N, A->flag.as<int>(), s);
+        LAUNCHCHK();
+    }
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, A->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) return fail(HELM_EINVAL, "velocity c has a non-finite or non-positive value");
+    return HELM_OK;
+}
+
 extern "C" int helm_assemble(const helm_params* p, const double* c, void* stream, helm_problem_t* out) {
     int B = 0;
     int rc = check_params(p, &B);
@@ -164,18 +225,8 @@ extern "C" int helm_assemble(const helm_params* p, const double* c, void* stream
     if ((rc = A->ic2.alloc(sizeof(double) * N))) return rc;
     if ((rc = A->flag.alloc(sizeof(int)))) return rc;
     if ((rc = A->pd.alloc(sizeof(ProbDev)))) return rc;
-    HIPCHK(hipMemsetAsync(A->flag.p, 0, sizeof(int), s));
+    if ((rc = assemble_into(A.get(), c, s))) return rc;
     const double h = A->h;
-    const double eta_p = (p->b_convention == 0 ? p->pml_w + 1 : p->pml_w) * h;
-    const double eta_m = B * h;
-    launch_profiles(A->lay, A->tab.as<double2>(), h, p->omega, eta_p, eta_m, p->pml_C, s);
-    LAUNCHCHK();
-    launch_inv_c2(c, A->ic2.as<double>(), N, A->flag.as<int>(), s);
-    LAUNCHCHK();
-    int bad = 0;
-    HIPCHK(hipMemcpyAsync(&bad, A->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (bad) return fail(HELM_EINVAL, "velocity c has a non-finite or non-positive value");
     ProbDev& P = A->host;
     P.n = n; P.B = B; P.c = A->c; P.L_lo = A->L_lo; P.L_up = A->L_up; P.nsub = A->nsub;
     P.ih2 = 1.0 / (h * h);
@@ -194,6 +245,11 @@ extern "C" int helm_assemble(const helm_params* p, const double* c, void* stream
     return HELM_OK;
 }
 
+extern "C" int helm_reassemble(helm_problem_t A, const double* c, void* stream) {
+    if (!A || !c) return fail(HELM_EINVAL, "NULL argument");
+    return assemble_into(A, c, (hipStream_t)stream);
+}
+
 extern "C" int helm_problem_n(helm_problem_t A) { return A ? A->n : -1; }
 
 extern "C" void helm_free(helm_problem_t A) { delete A; }
@@ -204,6 +260,7 @@ extern "C" int helm_matvec(helm_problem_t A, const void* x, int32_t x_prec, void
     if (x_prec != HELM_C128 && x_prec != HELM_C64) return fail(HELM_EINVAL, "x_prec must be HELM_C128 or HELM_C64");
     if (nrhs == 0) return HELM_OK;
     MvDev mv{x, y, nullptr, nrhs, 0};
+    PhaseScope ph(PH_MATVEC, (hipStream_t)stream);
     launch_matvec(A->pd.as<ProbDev>(), nullptr, mv, nullptr, 1, matvec_blocks(A->n), x_prec, (hipStream_t)stream);
     LAUNCHCHK();
     return HELM_OK;
@@ -212,6 +269,29 @@ extern "C" int helm_matvec(helm_problem_t A, const void* x, int32_t x_prec, void
 // ------------------------------------------------------------------------------------------------
 // a2: factorisation
 // ------------------------------------------------------------------------------------------------
+// Run the a2 kernels for every strip of M's problem and check the pivots.
+static int factor_into(sweep_factors_t M, hipStream_t s) {
+    helm_problem_t A = M->A;
+    const int n = A->n, B = A->B;
+    HIPCHK(hipMemsetAsync(M->status.p, 0, sizeof(int), s));
+    const ProbDev* pd = A->pd.as<ProbDev>();
+    {
+        PhaseScope ph(PH_FACTOR, s, 2);
+        if (!launch_factor(B, M->prec, pd, M->subs.as<SubDev>(), A->nsub - 1, n, M->fac.p, M->status.as<int>(), s))
+            return fail(HELM_EINVAL, "no factor kernel for B=%d", B);
+        LAUNCHCHK();
+        if (!launch_factor(2 * B - 1, M->prec, pd, M->subs.as<SubDev>() + (A->nsub - 1), 1, n, M->fac.p,
+                           M->status.as<int>(), s))
+            return fail(HELM_EINVAL, "no factor kernel for middle height %d", 2 * B - 1);
+        LAUNCHCHK();
+    }
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, M->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) return fail(HELM_ESINGULAR, "zero or non-finite pivot while inverting a diagonal block");
+    return HELM_OK;
+}
+
 extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_factors_t* out) {
     if (!A || !out) return fail(HELM_EINVAL, "NULL argument");
     if (prec != HELM_C128 && prec != HELM_C64) return fail(HELM_EINVAL, "prec must be HELM_C128 or HELM_C64");
@@ -220,43 +300,59 @@ extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_
     M->A = A;
     M->prec = prec;
     const int n = A->n, B = A->B;
-    const int64_t pk = packed_size(B), pkm = packed_size(2 * B - 1);
+    // stored column length (packed block + coupling scalars, padded to 16 bytes) per precision
+    const int64_t pk = prec == HELM_C128 ? col_stride<double>(B) : col_stride<float>(B);
+    const int64_t pkm = prec == HELM_C128 ? col_stride<double>(2 * B - 1) : col_stride<float>(2 * B - 1);
     M->fac_elems = (int64_t)(A->nsub - 1) * n * pk + (int64_t)n * pkm;
     const size_t esz = prec == HELM_C128 ? sizeof(double2) : sizeof(float2);
     int rc;
     if ((rc = M->fac.alloc(esz * (size_t)M->fac_elems))) return rc;
-    // strip descriptors: F, lower layers, E, upper layers (all height B), then the middle (2B-1)
+    // strip descriptors: F, lower layers, E, upper layers (all height B), then the middle (2B-1).
+    // Consecutive layers of a front alternate their column direction; jprev / jnext are the layer
+    // rows before and after each layer in its front's sweep (the middle row after the last one).
     auto& S = M->hsubs;
     S.clear();
+    const int c = A->c;
     for (int t = 0; t <= A->L_lo; ++t) {
         const int jl = B + t;
-        S.push_back(SubDev{0, t == 0 ? SUB_PHYS : SUB_MOVE, jl - (B - 1), 1, (int64_t)S.size() * n * pk});
+        S.push_back(SubDev{0, t == 0 ? SUB_PHYS : SUB_MOVE, jl - (B - 1), 1, (t & 1) ? -1 : 1, jl,
+                           t >= 1 ? jl - 1 : 0, t < A->L_lo ? jl + 1 : c, (int64_t)S.size() * n * pk});
     }
     for (int t = 0; t <= A->L_up; ++t) {
         const int jl = n + 1 - B - t;
-        S.push_back(SubDev{0, t == 0 ? SUB_PHYS : SUB_MOVE, jl + (B - 1), -1, (int64_t)S.size() * n * pk});
+        S.push_back(SubDev{0, t == 0 ? SUB_PHYS : SUB_MOVE, jl + (B - 1), -1, (t & 1) ? -1 : 1, jl,
+                           t >= 1 ? jl + 1 : 0, t < A->L_up ? jl - 1 : c, (int64_t)S.size() * n * pk});
     }
-    S.push_back(SubDev{0, SUB_MID, A->c - B + 1, 1, (int64_t)S.size() * n * pk});
+    S.push_back(SubDev{0, SUB_MID, c - B + 1, 1, 1, c, c - 1, c + 1, (int64_t)S.size() * n * pk});
+    // resolve each strip's x2 profile to plain pointers into the problem's profile tables
+    const ProbDev& P = A->host;
+    for (SubDev& d : S) {
+        if (d.kind == SUB_PHYS) {
+            const int i0 = d.j0 - 1;                         // 0-based physical row of local row 0
+            d.rs2 = P.s2n + i0; d.ris2 = P.is2n + i0; d.rstep = d.dir;
+            // half rows: s2h[j-1] lies below row j and s2h[j] above it (in the +x2 direction)
+            d.rlo = d.dir > 0 ? P.s2h + i0 : P.s2h + i0 + 1;
+            d.rhi = d.dir > 0 ? P.s2h + i0 + 1 : P.s2h + i0;
+        } else if (d.kind == SUB_MOVE) {
+            d.rs2 = P.mvn; d.ris2 = P.imvn; d.rlo = P.mvh; d.rhi = P.mvh + 1; d.rstep = 1;
+        } else {
+            d.rs2 = P.mdn; d.ris2 = P.imdn; d.rlo = P.mdh; d.rhi = P.mdh + 1; d.rstep = 1;
+        }
+    }
     M->sub_rows.assign(S.size(), B);
     M->sub_rows.back() = 2 * B - 1;
     if ((int)S.size() != A->nsub) return fail(HELM_EINVAL, "internal: subproblem count");
     if ((rc = M->subs.alloc(sizeof(SubDev) * S.size()))) return rc;
     if ((rc = M->status.alloc(sizeof(int)))) return rc;
     HIPCHK(hipMemcpy(M->subs.p, S.data(), sizeof(SubDev) * S.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemsetAsync(M->status.p, 0, sizeof(int), s));
-    const ProbDev* pd = A->pd.as<ProbDev>();
-    if (!launch_factor(B, prec, pd, M->subs.as<SubDev>(), A->nsub - 1, n, M->fac.p, M->status.as<int>(), s))
-        return fail(HELM_EINVAL, "no factor kernel for B=%d", B);
-    LAUNCHCHK();
-    if (!launch_factor(2 * B - 1, prec, pd, M->subs.as<SubDev>() + (A->nsub - 1), 1, n, M->fac.p, M->status.as<int>(), s))
-        return fail(HELM_EINVAL, "no factor kernel for middle height %d", 2 * B - 1);
-    LAUNCHCHK();
-    int st = 0;
-    HIPCHK(hipMemcpyAsync(&st, M->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (st) return fail(HELM_ESINGULAR, "zero or non-finite pivot while inverting a diagonal block");
+    if ((rc = factor_into(M.get(), s))) return rc;
     *out = M.release();
     return HELM_OK;
+}
+
+extern "C" int sweep_refactor(sweep_factors_t M, void* stream) {
+    if (!M) return fail(HELM_EINVAL, "NULL argument");
+    return factor_into(M, (hipStream_t)stream);
 }
 
 extern "C" int64_t sweep_factor_bytes(sweep_factors_t M) { return M ? (int64_t)M->fac.bytes : 0; }
@@ -270,13 +366,25 @@ extern "C" void sweep_free(sweep_factors_t M) { delete M; }
 
 static size_t compute_elem(int prec) { return prec == HELM_C128 ? sizeof(double2) : sizeof(float2); }
 
+// Right-hand sides per wave and the k-split of a launch: with a single right-hand side per problem
+// every row group of a wave works on it (split block-vector products); otherwise one right-hand
+// side per row group.
+static void rhs_grouping(int B, int max_nrhs, int* Q, int* ks, int* Qm, int* ksm) {
+    const int q = chain_rhs_per_wave(B), qm = middle_rhs_per_wave(B);
+    *ks = max_nrhs == 1 ? q : 1;
+    *ksm = max_nrhs == 1 ? qm : 1;
+    *Q = q / *ks;
+    *Qm = qm / *ksm;
+}
+
 // Single-problem chain tables: groups of Q right-hand sides per front, Qm per middle wave.
 static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
     helm_problem_t A = M->A;
     const int n = A->n, B = A->B;
-    const int Q = chain_rhs_per_wave(B), Qm = middle_rhs_per_wave(B);
+    int Q, Qm;
+    rhs_grouping(B, nrhs, &Q, &M->ks_chain, &Qm, &M->ks_mid);
     const int groups = (nrhs + Q - 1) / Q, mgroups = (nrhs + Qm - 1) / Qm;
-    const int64_t per = (int64_t)n * 64;
+    const int64_t per = (int64_t)n * 64 * 2;
     const size_t need = compute_elem(M->prec) * (size_t)per * (size_t)std::max(2 * groups, mgroups);
     int rc;
     if (M->spill.bytes < need) {
@@ -312,13 +420,25 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
     const ProbDev* pd = M->A->pd.as<ProbDev>();
     IoDev io{f, u, M->fac.p};
     const int B = M->A->B;
-    if (!launch_chains(B, M->prec, vec_prec, vec_prec, 0, pd, M->chains.as<ChainDev>(), M->nchains, nullptr, io, M->spill.p, s))
-        return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
-    LAUNCHCHK();
-    launch_middle(B, M->prec, vec_prec, vec_prec, pd, M->mids.as<ChainDev>(), M->nmids, nullptr, io, M->spill.p, s);
-    LAUNCHCHK();
-    launch_chains(B, M->prec, vec_prec, vec_prec, 1, pd, M->chains.as<ChainDev>(), M->nchains, nullptr, io, M->spill.p, s);
-    LAUNCHCHK();
+    {
+        PhaseScope ph(PH_SWEEP_FWD, s);
+        if (!launch_chains(B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
+                           nullptr, io, M->spill.p, s))
+            return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
+        LAUNCHCHK();
+    }
+    {
+        PhaseScope ph(PH_SWEEP_MID, s);
+        launch_middle(B, M->prec, vec_prec, vec_prec, M->ks_mid, pd, M->mids.as<ChainDev>(), M->nmids, nullptr, io,
+                      M->spill.p, s);
+        LAUNCHCHK();
+    }
+    {
+        PhaseScope ph(PH_SWEEP_BWD, s);
+        launch_chains(B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains, nullptr,
+                      io, M->spill.p, s);
+        LAUNCHCHK();
+    }
     return HELM_OK;
 }
 
@@ -330,7 +450,7 @@ extern "C" int sweep_subsolve(sweep_factors_t M, int32_t sub, const void* g, voi
     const int bs = M->sub_rows[sub];
     const int Q = 64 / chain_padded_rows(bs);
     const int groups = (nrhs + Q - 1) / Q;
-    const size_t need = compute_elem(M->prec) * (size_t)M->A->n * 64 * groups;
+    const size_t need = compute_elem(M->prec) * (size_t)M->A->n * 64 * 2 * groups;
     int rc;
     if (M->spill.bytes < need) {
         HIPCHK(hipStreamSynchronize(s));
@@ -339,7 +459,8 @@ extern "C" int sweep_subsolve(sweep_factors_t M, int32_t sub, const void* g, voi
     const SubDev& S = M->hsubs[sub];
     const size_t esz = M->prec == HELM_C128 ? sizeof(double2) : sizeof(float2);
     const char* fac = (const char*)M->fac.p + esz * S.fac_off;
-    if (!launch_subsolve(bs, M->prec, M->A->pd.as<ProbDev>(), fac, S.kind, S.j0, S.dir, g, x, nrhs, M->spill.p, s))
+    if (!launch_subsolve(bs, M->prec, M->A->pd.as<ProbDev>(), fac, S.ris2, S.rstep, S.cdir, S.jl, g, x, nrhs,
+                         M->spill.p, s))
         return fail(HELM_EINVAL, "no strip kernel for height %d", bs);
     LAUNCHCHK();
     return HELM_OK;
@@ -390,7 +511,8 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
     if ((rc = b->probs.alloc(sizeof(ProbDev) * count))) return rc;
     HIPCHK(hipMemcpy(b->probs.p, pdv.data(), sizeof(ProbDev) * count, hipMemcpyHostToDevice));
     // chains (longest first), middles
-    const int Q = chain_rhs_per_wave(B), Qm = middle_rhs_per_wave(B);
+    int Q, Qm;
+    rhs_grouping(B, *std::max_element(b->nrhs.begin(), b->nrhs.end()), &Q, &b->ks_chain, &Qm, &b->ks_mid);
     std::vector<int> order(count);
     for (int p = 0; p < count; ++p) order[p] = p;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return A[a]->n > A[c]->n; });
@@ -400,13 +522,13 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
         for (int g = 0; g * Q < b->nrhs[p]; ++g)
             for (int f = 0; f < 2; ++f) {
                 ch.push_back(ChainDev{p, f, g * Q, std::min(Q, b->nrhs[p] - g * Q), so});
-                so += (int64_t)A[p]->n * 64;
+                so += (int64_t)A[p]->n * 64 * 2;
             }
     int64_t mo = 0;
     for (int p : order)
         for (int g = 0; g * Qm < b->nrhs[p]; ++g) {
             md.push_back(ChainDev{p, 0, g * Qm, std::min(Qm, b->nrhs[p] - g * Qm), mo});
-            mo += (int64_t)A[p]->n * 64;
+            mo += (int64_t)A[p]->n * 64 * 2;
         }
     b->nchains = (int)ch.size();
     b->nmids = (int)md.size();
@@ -472,18 +594,56 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
 
 extern "C" void helm_batch_free(helm_batch_t b) { delete b; }
 
+extern "C" int helm_timing_enable(int32_t on) {
+    timing().on = on != 0;
+    return HELM_OK;
+}
+
+extern "C" int helm_timing_read(double* ms, int64_t* launches, int32_t reset) {
+    Timing& T = timing();
+    std::vector<double> acc(PH_N, 0.0);
+    std::vector<int64_t> cnt(PH_N, 0);
+    for (const TimerRec& r : T.recs) {
+        HIPCHK(hipEventSynchronize(r.b));
+        float e = 0.f;
+        HIPCHK(hipEventElapsedTime(&e, r.a, r.b));
+        acc[r.phase] += e;
+        cnt[r.phase] += r.launches;
+    }
+    for (int i = 0; i < PH_N; ++i) {
+        if (ms) ms[i] = acc[i];
+        if (launches) launches[i] = cnt[i];
+    }
+    if (reset) {
+        for (const TimerRec& r : T.recs) { T.pool.push_back(r.a); T.pool.push_back(r.b); }
+        T.recs.clear();
+    }
+    return HELM_OK;
+}
+
 // Enqueue M_alpha on the batch: io table `io` (device, one entry per problem), in complex128,
 // out complex128 or complex64 (the factor precision for FGMRES directions).
 static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, hipStream_t s) {
     const ProbDev* pd = b->probs.as<ProbDev>();
     const IoDev none{nullptr, nullptr, nullptr};
-    if (!launch_chains(b->B, b->prec, 0, out_prec, 0, pd, b->chains.as<ChainDev>(), b->nchains, io, none, b->spill.p, s))
-        return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
-    LAUNCHCHK();
-    launch_middle(b->B, b->prec, 0, out_prec, pd, b->mids.as<ChainDev>(), b->nmids, io, none, b->spill.p, s);
-    LAUNCHCHK();
-    launch_chains(b->B, b->prec, 0, out_prec, 1, pd, b->chains.as<ChainDev>(), b->nchains, io, none, b->spill.p, s);
-    LAUNCHCHK();
+    {
+        PhaseScope ph(PH_SWEEP_FWD, s);
+        if (!launch_chains(b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
+                           b->spill.p, s))
+            return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
+        LAUNCHCHK();
+    }
+    {
+        PhaseScope ph(PH_SWEEP_MID, s);
+        launch_middle(b->B, b->prec, 0, out_prec, b->ks_mid, pd, b->mids.as<ChainDev>(), b->nmids, io, none, b->spill.p, s);
+        LAUNCHCHK();
+    }
+    {
+        PhaseScope ph(PH_SWEEP_BWD, s);
+        launch_chains(b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
+                      b->spill.p, s);
+        LAUNCHCHK();
+    }
     return HELM_OK;
 }
 
@@ -549,10 +709,16 @@ extern "C" int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* co
     const int hstride = kk + 1;
     while (true) {
         // r = f - A u (into W), beta = ||r||
-        launch_matvec(pd, b->mv_res.as<MvDev>(), none, b->mv_blk.as<int32_t>(), b->count, b->mv_blocks, 0, s);
-        LAUNCHCHK();
-        launch_norms(dsv, dt, ns, nt, 0, b->partial.as<double2>(), b->beta.as<double>(), nullptr, s);
-        LAUNCHCHK();
+        {
+            PhaseScope ph(PH_MATVEC, s);
+            launch_matvec(pd, b->mv_res.as<MvDev>(), none, b->mv_blk.as<int32_t>(), b->count, b->mv_blocks, 0, s);
+            LAUNCHCHK();
+        }
+        {
+            PhaseScope ph(PH_KRYLOV, s, 2);
+            launch_norms(dsv, dt, ns, nt, 0, b->partial.as<double2>(), b->beta.as<double>(), nullptr, s);
+            LAUNCHCHK();
+        }
         HIPCHK(hipMemcpyAsync(bet.data(), b->beta.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         int nact = 0;
@@ -573,24 +739,30 @@ extern "C" int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* co
         for (int j = 0; j < kk; ++j) {
             int rc = batch_sweep(b, b->io_sweep.as<IoDev>() + (size_t)j * b->count, zprec, s);
             if (rc) return rc;
-            launch_matvec(pd, b->mv_z.as<MvDev>() + (size_t)j * b->count, none, b->mv_blk.as<int32_t>(), b->count,
-                          b->mv_blocks, zprec, s);
-            LAUNCHCHK();
-            double2* Hcol = b->H.as<double2>() + (size_t)j * (kk + 1);   // system stride kk*(kk+1)
-            const int hs_ = kk * (kk + 1);
-            // classical Gram-Schmidt, twice
-            launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, b->active.as<int32_t>(), s);
-            launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 0, s);
-            launch_multiaxpy(dsv, dt, ns, nt, j, Hcol, hs_, b->active.as<int32_t>(), s);
-            launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, b->active.as<int32_t>(), s);
-            launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, b->hbuf.as<double2>(), hstride, 0, s);
-            launch_multiaxpy(dsv, dt, ns, nt, j, b->hbuf.as<double2>(), hstride, b->active.as<int32_t>(), s);
-            launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 1, s);
-            launch_norms(dsv, dt, ns, nt, 0, b->partial.as<double2>(), b->nrm.as<double>(), b->active.as<int32_t>(), s);
-            launch_arnoldi_finish(ns, j, kk, b->H.as<double2>(), b->cs.as<double2>(), b->g.as<double2>(),
-                                  b->nrm.as<double>(), b->inv.as<double>(), b->est.as<double>(), b->active.as<int32_t>(), s);
-            launch_scale_to_v(dsv, dt, ns, nt, j + 1, b->inv.as<double>(), b->active.as<int32_t>(), s);
-            LAUNCHCHK();
+            {
+                PhaseScope ph(PH_MATVEC, s);
+                launch_matvec(pd, b->mv_z.as<MvDev>() + (size_t)j * b->count, none, b->mv_blk.as<int32_t>(), b->count,
+                              b->mv_blocks, zprec, s);
+                LAUNCHCHK();
+            }
+            {
+                PhaseScope phk(PH_KRYLOV, s, 12);
+                double2* Hcol = b->H.as<double2>() + (size_t)j * (kk + 1);   // system stride kk*(kk+1)
+                const int hs_ = kk * (kk + 1);
+                // classical Gram-Schmidt, twice
+                launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, b->active.as<int32_t>(), s);
+                launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 0, s);
+                launch_multiaxpy(dsv, dt, ns, nt, j, Hcol, hs_, b->active.as<int32_t>(), s);
+                launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, b->active.as<int32_t>(), s);
+                launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, b->hbuf.as<double2>(), hstride, 0, s);
+                launch_multiaxpy(dsv, dt, ns, nt, j, b->hbuf.as<double2>(), hstride, b->active.as<int32_t>(), s);
+                launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 1, s);
+                launch_norms(dsv, dt, ns, nt, 0, b->partial.as<double2>(), b->nrm.as<double>(), b->active.as<int32_t>(), s);
+                launch_arnoldi_finish(ns, j, kk, b->H.as<double2>(), b->cs.as<double2>(), b->g.as<double2>(),
+                                      b->nrm.as<double>(), b->inv.as<double>(), b->est.as<double>(), b->active.as<int32_t>(), s);
+                launch_scale_to_v(dsv, dt, ns, nt, j + 1, b->inv.as<double>(), b->active.as<int32_t>(), s);
+                LAUNCHCHK();
+            }
             HIPCHK(hipMemcpyAsync(est.data(), b->est.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             int still = 0;

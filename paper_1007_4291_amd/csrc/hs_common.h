@@ -53,6 +53,35 @@ template <class To, class Ti> __host__ __device__ __forceinline__ C2<To> ccast(C
     return mk<To>((To)a.x, (To)a.y);
 }
 
+// Pointers read from descriptor tables are generic; accessing device memory through them as
+// global-address-space pointers gives global_load/store (counted by vmcnt only) instead of flat
+// operations, whose completion also gates every LDS wait.
+#define HS_GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ HS_GLOBAL T* gptr(T* p) { return (HS_GLOBAL T*)p; }
+template <class T> __device__ __forceinline__ const HS_GLOBAL T* gptr(const T* p) { return (const HS_GLOBAL T*)p; }
+// complex loads / stores through global pointers (HIP's vector types cannot be copied across
+// address spaces, so the access goes through native vector types)
+typedef double hs_d2v __attribute__((ext_vector_type(2)));
+typedef float hs_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 gld(const HS_GLOBAL double2* p) {
+    const hs_d2v v = *(const HS_GLOBAL hs_d2v*)p;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 gld(const HS_GLOBAL float2* p) {
+    const hs_f2v v = *(const HS_GLOBAL hs_f2v*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(HS_GLOBAL double2* p, double2 v) {
+    hs_d2v w;
+    w.x = v.x; w.y = v.y;
+    *(HS_GLOBAL hs_d2v*)p = w;
+}
+__device__ __forceinline__ void gst(HS_GLOBAL float2* p, float2 v) {
+    hs_f2v w;
+    w.x = v.x; w.y = v.y;
+    *(HS_GLOBAL hs_f2v*)p = w;
+}
+
 // ---------------------------------------------------------------------------------------------
 // descriptors
 // ---------------------------------------------------------------------------------------------
@@ -77,7 +106,17 @@ struct SubDev {
     int32_t prob;       // index into the ProbDev table
     int32_t kind;       // SubKind
     int32_t j0, dir;    // physical row (1-based) of local row 0, and +1/-1 going up the local rows
+    int32_t cdir;       // column direction of the block LU: +1 (1 -> n) or -1 (n -> 1)
+    int32_t jl;         // layer row of the strip (the row whose values leave the strip)
+    int32_t jprev;      // layer row of the previous layer in the sweep (0: none)
+    int32_t jnext;      // layer row of the next layer in the sweep (0: none)
     int64_t fac_off;    // offset of this strip's factor (in complex elements)
+    // The strip's x2 profile resolved on the host (no branch on the strip kind in device code):
+    // local row r has s2 = rs2[rstep*r], 1/s2 = ris2[rstep*r], and s2 at the half rows below and
+    // above it rlo[rstep*r], rhi[rstep*r].
+    const double2 *rs2, *ris2, *rlo, *rhi;
+    int32_t rstep;
+    int32_t pad_;
 };
 
 // One sweep chain: a front of one problem and a group of right-hand sides.
@@ -96,10 +135,35 @@ struct IoDev {
 };
 
 __host__ __device__ constexpr int packed_size(int bs) { return bs * (bs + 1) / 2; }
+
+// Lanes per strip row group: a strip of BS rows occupies RP lanes (padded), Q = 64/RP groups per wave.
+template <int BS> struct RowsOf {
+    static constexpr int RP = BS <= 16 ? 16 : (BS <= 32 ? 32 : 64);
+    static constexpr int Q = 64 / RP;
+};
+
+// One stored column of a strip factor: the packed upper triangle of Lambda_s^{-1} (PACK entries),
+// then three coupling scalars (x1 coupling to the next step without the 1/s2 row factor;
+// coupling of the layer row to the previous / next layer), padded to a multiple of 16 bytes.
+constexpr int XCOL_E = 0, XCOL_APREV = 1, XCOL_ANEXT = 2;
+template <class TF> __host__ __device__ constexpr int col_stride(int bs) {
+    return sizeof(C2<TF>) == 8 ? ((packed_size(bs) + 3 + 1) & ~1) : packed_size(bs) + 3;
+}
 // index of (r, k), r <= k, in the row-major packed upper triangle of a bs x bs block
 __host__ __device__ constexpr int packed_index(int bs, int r, int k) { return r * bs - (r * (r - 1)) / 2 + (k - r); }
 
-// Profile of local row r of a strip: s2, 1/s2 at the row and s2 at the half rows below / above it.
+// Profile of local row r of a strip described by a SubDev.
+__device__ __forceinline__ void row_profile(const SubDev& S, int r, double2& s2, double2& is2, double2& s2lo,
+                                            double2& s2hi) {
+    const int o = S.rstep * r;
+    s2 = gld(gptr(S.rs2 + o));
+    is2 = gld(gptr(S.ris2 + o));
+    s2lo = gld(gptr(S.rlo + o));
+    s2hi = gld(gptr(S.rhi + o));
+}
+
+// Profile of local row r of a strip of a kind fixed at compile time: s2, 1/s2 at the row and s2 at
+// the half rows below / above it.
 __device__ __forceinline__ void strip_profile(const ProbDev& P, int kind, int j0, int dir, int r,
                                               double2& s2, double2& is2, double2& s2lo, double2& s2hi) {
     if (kind == SUB_PHYS) {

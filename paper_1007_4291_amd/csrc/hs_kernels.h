@@ -54,19 +54,21 @@ bool launch_factor(int bs, int prec, const ProbDev* prob, const SubDev* subs, in
 //   phase 1: backward substitution along each chain
 // vec_in/vec_out precisions: 0 complex128, 1 complex64.  Factor precision `prec`.
 // io: device table indexed by ChainDev::prob, or nullptr to use io_val for every chain.
-bool launch_chains(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
+// ksplit: 1 (each 16/32/64-lane row group serves its own right-hand side) or the number of row
+// groups per wave (all groups serve one right-hand side, splitting each block-vector product).
+bool launch_chains(int B, int prec, int in_prec, int out_prec, int phase, int ksplit, const ProbDev* probs,
                    const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s);
-bool launch_middle(int B, int prec, int in_prec, int out_prec, const ProbDev* probs,
+bool launch_middle(int B, int prec, int in_prec, int out_prec, int ksplit, const ProbDev* probs,
                    const ChainDev* mids, int nmids, const IoDev* io, IoDev io_val, void* spill, hipStream_t s);
 // Lanes per row group (right-hand sides per wave) for chains of strip height B and for the middle.
 int chain_rhs_per_wave(int B);
 int middle_rhs_per_wave(int B);
-// Padded rows per right-hand side inside a wave (the spill workspace is n * 64 complex per chain).
+// Padded rows per right-hand side inside a wave (each chain's workspace is 2 * n * 64 complex).
 int chain_padded_rows(int B);
 
 // Test hook: full-input / full-output solve of one strip (complex128 vectors [nrhs][rows][n]).
-bool launch_subsolve(int bs, int prec, const ProbDev* prob, const void* fac, int kind, int j0,
-                     int dir, const void* g, void* x, int nrhs, void* spill, hipStream_t s);
+bool launch_subsolve(int bs, int prec, const ProbDev* prob, const void* fac, const double2* ris2, int rstep, int cdir,
+                     int jl, const void* g, void* x, int nrhs, void* spill, hipStream_t s);
 
 // ---- FGMRES building blocks (a6), batched over systems --------------------------------------
 // A "system" is one right-hand side of one problem.  Vectors of system s start at base[s] and have

@@ -1,316 +1,428 @@
 // a3 / a4: application of the approximate sweeping LDL^t (Algorithm 4, two fronts + middle layer).
 //
-// One wavefront runs one chain (a front of one problem) for a group of right-hand sides.  Lane
-// (q, r) = lane / RP, lane % RP owns row r of the strip for right-hand side q.  Each strip solve is
-// the block LU solve over the n columns:
-//   forward   w_i = Lambda_i^{-1} z_i,  z_{i+1} = g_{i+1} - e_{i+1} w_i     (w kept in a workspace)
-//   backward  x_n = w_n,  x_i = w_i - Lambda_i^{-1} (e_{i+1} x_{i+1})
-// The block-vector products exchange z through LDS; Lambda_i^{-1} rows are gathered from the
-// packed symmetric store one column ahead of their use.
+// One wavefront runs one chain: the layers of one front of one problem, in the order of a phase
+// (forward substitution: F, B+1, ..., c-1; backward substitution: c-1, ..., B+1, F; likewise for the
+// downward front), for a group of right-hand sides.  Lane (q, r) = (lane / RP, lane % RP) owns row r
+// of the strip for right-hand side q.  Each strip solve is the block LU solve along the strip's
+// column direction (step s = 0..n-1):
+//   forward   w_s = Lambda_s^{-1} z_s,   z_{s+1} = g_{s+1} - e_{s,s+1} w_s      (w kept in a workspace)
+//   backward  x_{n-1} = w_{n-1},  x_s = w_s - Lambda_s^{-1} (e_{s,s+1} x_{s+1})
+// Consecutive layers of a front are factored in opposite column directions, so the backward pass of
+// layer t emits its layer-row values in exactly the column order in which the forward pass of layer
+// t+1 consumes them: the two passes run in lockstep, one column ("tick") apart, two independent
+// block-vector products per tick.  Factor columns, workspace values and inputs are prefetched D ticks
+// ahead through a register ring and staged in LDS; the block-vector products exchange vectors in LDS.
+#include <utility>
+
 #include "hs_common.h"
 #include "hs_kernels.h"
 
 namespace hs {
 
-template <int BS> struct PadRows { static constexpr int v = BS <= 16 ? 16 : (BS <= 32 ? 32 : 64); };
-
-// Row r of the packed symmetric block at `col` (BS entries, zero for padding lanes).
-template <class T, class TF, int BS>
-__device__ __forceinline__ void load_row(const C2<TF>* __restrict__ col, int r, bool rowok, C2<T> (&L)[BS]) {
-    r = rowok ? r : 0;
-#pragma unroll
-    for (int k = 0; k < BS; ++k) {
-        const int idx = (k >= r) ? (r * BS - (r * (r - 1)) / 2 + (k - r)) : (k * BS - (k * (k - 1)) / 2 + (r - k));
-        L[k] = rowok ? ccast<T, TF>(col[idx]) : mk<T>(0, 0);
-    }
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N-1>): a loop unrolled at compile time
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F> __device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// Block LU solve of one strip for the lane's (row, rhs); loadg(i) gives g at column i (1-based)
-// for this lane, storex(i, x) receives the solution.  is2: 1/s2 of the lane's row.
-template <class T, class TF, int BS, int RP, class LoadG, class StoreX>
-__device__ __forceinline__ void strip_solve(const ProbDev& P, const C2<TF>* __restrict__ fac, double2 is2,
-                                            C2<T>* __restrict__ spill, C2<T> (*zx)[64 / RP][RP],
-                                            LoadG loadg, StoreX storex) {
-    constexpr int PACK = packed_size(BS);
-    const int lane = threadIdx.x, r = lane % RP, q = lane / RP;
-    const bool rowok = r < BS;
-    const int n = P.n;
-    const double ih2 = P.ih2;
-    const double2 is2h = cscale<double>(is2, ih2);
+enum SweepMode : int { MODE_FWD = 0, MODE_BWD = 1, MODE_MID = 2, MODE_SUB = 3 };
 
-    C2<T> Lc[BS], Ln[BS];
-    load_row<T, TF, BS>(fac, r, rowok, Lc);
-    C2<T> z = loadg(1);
-    C2<T> w = mk<T>(0, 0);
-    int buf = 0;
-    for (int i = 1; i <= n; ++i) {
-        if (i < n) load_row<T, TF, BS>(fac + (int64_t)i * PACK, r, rowok, Ln);
-        zx[buf][q][r] = z;
-        __syncthreads();
-        C2<T> acc = mk<T>(0, 0);
-#pragma unroll
-        for (int k = 0; k < BS; ++k) acc = cfma<T>(Lc[k], zx[buf][q][k], acc);
-        w = acc;
-        spill[(int64_t)(i - 1) * 64 + lane] = w;
-        if (i < n) {
-            const C2<T> e = ccast<T, double>(cmul<double>(P.s1h[i], is2h));     // coupling of columns i, i+1
-            z = cfms<T>(e, w, loadg(i + 1));
-#pragma unroll
-            for (int k = 0; k < BS; ++k) Lc[k] = Ln[k];
-        }
-        buf ^= 1;
-    }
-    C2<T> x = w;
-    storex(n, x);
-    if (n > 1) load_row<T, TF, BS>(fac + (int64_t)(n - 2) * PACK, r, rowok, Lc);
-    for (int i = n - 1; i >= 1; --i) {
-        if (i > 1) load_row<T, TF, BS>(fac + (int64_t)(i - 2) * PACK, r, rowok, Ln);
-        const C2<T> e = ccast<T, double>(cmul<double>(P.s1h[i], is2h));
-        zx[buf][q][r] = cmul<T>(e, x);
-        __syncthreads();
-        C2<T> acc = spill[(int64_t)(i - 1) * 64 + lane];
-#pragma unroll
-        for (int k = 0; k < BS; ++k) acc = cfms<T>(Lc[k], zx[buf][q][k], acc);
-        x = acc;
-        storex(i, x);
-        if (i > 1) {
-#pragma unroll
-            for (int k = 0; k < BS; ++k) Lc[k] = Ln[k];
-        }
-        buf ^= 1;
-    }
-}
+// 16-byte chunk of a stored factor column (native vector type, kept in registers by the compiler)
+typedef unsigned int chunk16 __attribute__((ext_vector_type(4)));
 
-template <class T> __device__ __forceinline__ C2<T> ld(const double2* p) { return ccast<T, double>(*p); }
-template <class T> __device__ __forceinline__ C2<T> ld(const float2* p) { return ccast<T, float>(*p); }
+template <class TF, int BS> struct ColChunks {
+    static constexpr int STRIDE = col_stride<TF>(BS);
+    static constexpr int N16 = STRIDE * (int)sizeof(C2<TF>) / 16;   // 16-byte chunks per column
+    static constexpr int NCH = (N16 + 63) / 64;                      // chunks per lane
+};
+
+// One strip of the program a wave runs.
+struct StripRT {
+    const char* fac;    // first stored column
+    int d;              // column direction
+    int jl;             // layer row
+    int full;           // every row in / out (front blocks F, E and the test hook)
+    int kind, j0, rdir; // profile kind, physical row of local row 0, row direction
+};
+
+__device__ __forceinline__ double2 ld2(const HS_GLOBAL double2* p) { return gld(p); }
+__device__ __forceinline__ double2 ld2(const HS_GLOBAL float2* p) { const float2 v = gld(p); return make_double2(v.x, v.y); }
 template <class TO, class T> __device__ __forceinline__ TO cvt_out(C2<T> v);
 template <> __device__ __forceinline__ double2 cvt_out<double2, double>(double2 v) { return v; }
 template <> __device__ __forceinline__ double2 cvt_out<double2, float>(float2 v) { return make_double2(v.x, v.y); }
 template <> __device__ __forceinline__ float2 cvt_out<float2, float>(float2 v) { return v; }
 template <> __device__ __forceinline__ float2 cvt_out<float2, double>(double2 v) { return make_float2((float)v.x, (float)v.y); }
 
-// Coupling A_{j+1,j} at column i: (s2/s1)/h^2 at (ih, (j+1/2)h), j = the lower of the two rows.
-__device__ __forceinline__ double2 row_coupling(const ProbDev& P, int jlo, int i) {
-    return cscale<double>(cmul<double>(P.s2h[jlo], P.is1n[i - 1]), P.ih2);
-}
+struct SubArg {
+    const void* fac;
+    const double2* g;
+    double2* x;
+    const double2* ris2;    // 1/s2 of local row r at ris2[rstep * r]
+    int nrhs, rstep, cdir, jl;
+};
 
-template <class T, class TF, class TI, class TO, int BS>
-__global__ __launch_bounds__(64) void k_chain(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
-                                              const IoDev* __restrict__ io, IoDev io_val, int phase,
-                                              C2<T>* __restrict__ spill_base) {
-    constexpr int RP = PadRows<BS>::v;
-    constexpr int Q = 64 / RP;
+template <class T, class TF, class TI, class TO, int BS, int MODE, int D, int KS>
+__global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
+                                              const IoDev* __restrict__ io, IoDev io_val, C2<T>* __restrict__ spill_base,
+                                              SubArg sa) {
+    using CT = C2<T>;
+    using CF = C2<TF>;
+    constexpr int RP = RowsOf<BS>::RP, Q = RowsOf<BS>::Q;
+    using CC = ColChunks<TF, BS>;
+    constexpr int STRIDE = CC::STRIDE, N16 = CC::N16, NCH = CC::NCH;
     constexpr int PACK = packed_size(BS);
-    __shared__ C2<T> zx[2][Q][RP];
+    // forward products of the last LAG steps, needed by the first backward steps before the
+    // workspace copies written at the end of the previous pair can be prefetched
+    constexpr int LAG = (D - 1) / 2 > 0 ? (D - 1) / 2 : 1;
+    __shared__ chunk16 colb[N16];
+    __shared__ chunk16 colf[2][N16];
+    __shared__ CT xbx[Q][RP];
+    __shared__ CT xfx[Q][RP];
+
+    // lane = q * RP + r; with KS > 1 the KS groups q = KS*rq + kg share one right-hand side rq and
+    // split each row-dot product over k = kg, kg + KS, ... (combined by cross-group shuffles)
     const int lane = threadIdx.x, r = lane % RP, q = lane / RP;
-    const ChainDev ch = chains[blockIdx.x];
+    const int rq = q / KS, kg = q % KS;
+    constexpr int KMAX = (BS + KS - 1) / KS;
+    ChainDev ch{0, 0, 0, 0, 0};
+    if (MODE != MODE_SUB) ch = chains[blockIdx.x];
     const ProbDev& P = probs[ch.prob];
-    const IoDev D = io ? io[ch.prob] : io_val;
-    const int n = P.n, B = BS;
-    const int64_t N = (int64_t)n * n;
-    const bool qok = q < ch.nq;
-    const bool act = qok && r < BS;
-    const bool slot = act && r == B - 1;
-    const int rhs = ch.rhs0 + (qok ? q : 0);
-    const TI* __restrict__ fin = (const TI*)D.in + rhs * N;
-    TO* __restrict__ y = (TO*)D.out + rhs * N;
-    const C2<TF>* __restrict__ fac = (const C2<TF>*)D.fac;
-    C2<T>* __restrict__ spill = spill_base + ch.spill_off;
-    const int dir = ch.front == 0 ? 1 : -1;
-    const int jF = ch.front == 0 ? B : n + 1 - B;
+    const IoDev IO = io ? io[ch.prob] : io_val;
+    // problem scalars, loaded once
+    const int n = P.n, B = P.B, cmid = P.c, nsub = P.nsub;
     const int L = ch.front == 0 ? P.L_lo : P.L_up;
     const int sub0 = ch.front == 0 ? 0 : P.L_lo + 1;
-    const int64_t fstride = (int64_t)n * PACK;
-    const int rr = r < BS ? r : 0;
+    const int64_t N = (int64_t)n * n;
+    constexpr int QR = Q / KS;                                    // right-hand sides per wave
+    const int nq = MODE == MODE_SUB ? min(QR, sa.nrhs - (int)blockIdx.x * QR) : ch.nq;
+    const bool qok = rq < nq;
+    const bool rok = r < BS;
+    const bool act = qok && rok;                                  // lane holds a row of a live system
+    const bool own = act && kg == 0;                              // ... and writes it
+    const bool slot = (MODE == MODE_SUB) ? false : (act && r == B - 1);
+    const bool oslot = slot && kg == 0;
+    const int rhs = (MODE == MODE_SUB ? (int)blockIdx.x * QR : ch.rhs0) + (qok ? rq : 0);
+    const int rr = rok ? r : 0;
+    const HS_GLOBAL TI* __restrict__ fin = gptr((const TI*)IO.in + rhs * N);
+    HS_GLOBAL TO* __restrict__ y = gptr((TO*)IO.out + rhs * N);
+    HS_GLOBAL C2<T>* __restrict__ spill = gptr(spill_base + (MODE == MODE_SUB ? (int64_t)blockIdx.x * 2 * n * 64 : ch.spill_off));
+    const HS_GLOBAL char* const facbase = gptr(MODE == MODE_SUB ? (const char*)sa.fac : (const char*)IO.fac);
+    const HS_GLOBAL double2* const sag = gptr(sa.g);
+    HS_GLOBAL double2* const sax = gptr(sa.x);
 
-    auto strip = [&](int t, auto loadg, auto storex) {
-        const int jl = jF + dir * t;
-        const int j0 = jl - dir * (B - 1);
-        double2 s2, is2, s2lo, s2hi;
-        strip_profile(P, t == 0 ? SUB_PHYS : SUB_MOVE, j0, dir, rr, s2, is2, s2lo, s2hi);
-        strip_solve<T, TF, BS, RP>(P, fac + (int64_t)(sub0 + t) * fstride, is2, spill, zx, loadg, storex);
+    // the program: strips 0..m in processing order
+    const int dirF = ch.front == 0 ? 1 : -1;
+    const int jF = ch.front == 0 ? B : n + 1 - B;
+    const int64_t bstride = (int64_t)n * col_stride<TF>(B);          // elements per B-row strip
+    const int m = (MODE == MODE_FWD || MODE == MODE_BWD) ? L : 0;
+    auto strip_t = [&](int i) __attribute__((always_inline)) { return MODE == MODE_FWD ? i : L - i; };
+    auto strip_dir = [&](int i) __attribute__((always_inline)) -> int {   // also for the virtual strip m+1
+        if (MODE == MODE_FWD || MODE == MODE_BWD) return (strip_t(i) & 1) ? -1 : 1;
+        const int d0 = MODE == MODE_SUB ? sa.cdir : 1;
+        return i == 0 ? d0 : -d0;
     };
+    // first stored column of strip i (a valid address for every i in [0, m])
+    auto strip_fac = [&](int i) __attribute__((always_inline)) -> const HS_GLOBAL char* {
+        if (MODE == MODE_FWD || MODE == MODE_BWD) return facbase + sizeof(CF) * ((int64_t)(sub0 + strip_t(i)) * bstride);
+        if (MODE == MODE_MID) return facbase + sizeof(CF) * ((int64_t)(nsub - 1) * bstride);
+        return facbase;
+    };
+    auto strip_full = [&](int i) __attribute__((always_inline)) -> bool {
+        if (MODE == MODE_FWD || MODE == MODE_BWD) return strip_t(i) == 0;
+        return MODE == MODE_SUB;
+    };
+    // physical row of this lane (full strips) or of the layer row (others), 1-based
+    auto strip_row = [&](int i, bool full) __attribute__((always_inline)) -> int {
+        if (MODE == MODE_FWD || MODE == MODE_BWD) {
+            const int jl = jF + dirF * strip_t(i);
+            return full ? jl - dirF * (B - 1 - rr) : jl;
+        }
+        return cmid;
+    };
+    auto colof = [&](int d, int k) __attribute__((always_inline)) { return d > 0 ? k + 1 : n - k; };
 
-    if (phase == 0) {
-        // front block: all rows in, all rows out
-        {
-            const int jrow = jF - dir * (B - 1 - rr);
-            const TI* gin = fin + (int64_t)(jrow - 1) * n;
-            TO* xo = y + (int64_t)(jrow - 1) * n;
-            strip(0, [&](int i) { return act ? ld<T>(gin + i - 1) : mk<T>(0, 0); },
-                  [&](int i, C2<T> x) { if (act) xo[i - 1] = cvt_out<TO, T>(x); });
-        }
-        for (int t = 1; t <= L; ++t) {
-            const int jl = jF + dir * t, jp = jl - dir, jlo = jl < jp ? jl : jp;
-            const TI* gin = fin + (int64_t)(jl - 1) * n;
-            const TO* yp = y + (int64_t)(jp - 1) * n;
-            TO* xo = y + (int64_t)(jl - 1) * n;
-            strip(t,
-                  [&](int i) {
-                      if (!slot) return mk<T>(0, 0);
-                      const double2 a = row_coupling(P, jlo, i);
-                      return ccast<T, double>(cfms<double>(a, ld<double>(yp + i - 1), ld<double>(gin + i - 1)));
-                  },
-                  [&](int i, C2<T> x) { if (slot) xo[i - 1] = cvt_out<TO, T>(x); });
-        }
-    } else {
-        for (int t = L; t >= 0; --t) {
-            const int jl = jF + dir * t, jn = jl + dir, jlo = jl < jn ? jl : jn;
-            const TO* yn = y + (int64_t)(jn - 1) * n;
-            auto loadg = [&](int i) {
-                if (!slot) return mk<T>(0, 0);
-                return ccast<T, double>(cmul<double>(row_coupling(P, jlo, i), ld<double>(yn + i - 1)));
-            };
-            if (t > 0) {
-                TO* xo = y + (int64_t)(jl - 1) * n;
-                strip(t, loadg, [&](int i, C2<T> x) {
-                    if (slot) xo[i - 1] = cvt_out<TO, T>(csub<T>(ld<T>(xo + i - 1), x));
-                });
-            } else {
-                const int jrow = jF - dir * (B - 1 - rr);
-                TO* xo = y + (int64_t)(jrow - 1) * n;
-                strip(0, loadg, [&](int i, C2<T> x) {
-                    if (act) xo[i - 1] = cvt_out<TO, T>(csub<T>(ld<T>(xo + i - 1), x));
-                });
-            }
+    // 1/s2 of this lane's row: front blocks use the physical profile, moving layers the moving one
+    CT is2_front = mk<T>(0, 0), is2_other = mk<T>(0, 0);
+    {
+        double2 s2, is2, lo, hi;
+        if (MODE == MODE_FWD || MODE == MODE_BWD) {
+            strip_profile(P, SUB_PHYS, jF - dirF * (B - 1), dirF, rr, s2, is2, lo, hi);
+            is2_front = ccast<T, double>(is2);
+            strip_profile(P, SUB_MOVE, 0, 1, rr, s2, is2, lo, hi);
+            is2_other = ccast<T, double>(is2);
+        } else if (MODE == MODE_MID) {
+            strip_profile(P, SUB_MID, 0, 1, rr, s2, is2, lo, hi);
+            is2_other = ccast<T, double>(is2);
+        } else {
+            is2_other = ccast<T, double>(gld(gptr(sa.ris2 + sa.rstep * rr)));
         }
     }
-}
+    auto strip_is2 = [&](int i) __attribute__((always_inline)) -> CT {
+        if (MODE == MODE_FWD || MODE == MODE_BWD) return strip_t(i) == 0 ? is2_front : is2_other;
+        return is2_other;
+    };
 
-// Middle layer c: strip of 2B-1 rows damped on both sides; input u_c updated by both fronts.
-template <class T, class TF, class TI, class TO, int BSM>
-__global__ __launch_bounds__(64) void k_middle(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ mids,
-                                               const IoDev* __restrict__ io, IoDev io_val, C2<T>* __restrict__ spill_base) {
-    constexpr int RP = PadRows<BSM>::v;
-    constexpr int Q = 64 / RP;
-    __shared__ C2<T> zx[2][Q][RP];
-    const int lane = threadIdx.x, r = lane % RP, q = lane / RP;
-    const ChainDev ch = mids[blockIdx.x];
-    const ProbDev& P = probs[ch.prob];
-    const IoDev D = io ? io[ch.prob] : io_val;
-    const int n = P.n, B = P.B, c = P.c;
-    const int64_t N = (int64_t)n * n;
-    const bool qok = q < ch.nq;
-    const bool slot = qok && r == B - 1;
-    const int rhs = ch.rhs0 + (qok ? q : 0);
-    const TI* __restrict__ gin = (const TI*)D.in + rhs * N + (int64_t)(c - 1) * n;
-    TO* __restrict__ y = (TO*)D.out + rhs * N;
-    const TO* ylo = y + (int64_t)(c - 2) * n;
-    const TO* yhi = y + (int64_t)c * n;
-    TO* xo = y + (int64_t)(c - 1) * n;
-    const int64_t moff = (int64_t)(P.nsub - 1) * n * packed_size(B);
-    const C2<TF>* __restrict__ fac = (const C2<TF>*)D.fac + moff;
-    double2 s2, is2, s2lo, s2hi;
-    strip_profile(P, SUB_MID, c - B + 1, 1, r < BSM ? r : 0, s2, is2, s2lo, s2hi);
-    strip_solve<T, TF, BSM, RP>(P, fac, is2, spill_base + ch.spill_off, zx,
-        [&](int i) {
-            if (!slot) return mk<T>(0, 0);
-            double2 g = ld<double>(gin + i - 1);
-            g = cfms<double>(row_coupling(P, c - 1, i), ld<double>(ylo + i - 1), g);
-            g = cfms<double>(row_coupling(P, c, i), ld<double>(yhi + i - 1), g);
-            return ccast<T, double>(g);
-        },
-        [&](int i, C2<T> x) { if (slot) xo[i - 1] = cvt_out<TO, T>(x); });
-}
+    // register ring
+    chunk16 rbk[D][NCH], rfk[D][NCH];
+    CT rsp[D];
+    double2 ra[D], rb2[D], rc[D];
 
-// Test hook: one strip, every row in and out; vectors complex128 [nrhs][BS][n].
-template <class T, class TF, int BS>
-__global__ __launch_bounds__(64) void k_subsolve(const ProbDev* __restrict__ prob, const C2<TF>* __restrict__ fac,
-                                                 int kind, int j0, int dir, const double2* __restrict__ g,
-                                                 double2* __restrict__ x, int nrhs, C2<T>* __restrict__ spill) {
-    constexpr int RP = PadRows<BS>::v;
-    constexpr int Q = 64 / RP;
-    __shared__ C2<T> zx[2][Q][RP];
-    const int lane = threadIdx.x, r = lane % RP, q = lane / RP;
-    const ProbDev& P = *prob;
-    const int n = P.n;
-    const int rhs = blockIdx.x * Q + q;
-    const bool act = rhs < nrhs && r < BS;
-    const int64_t off = ((int64_t)(act ? rhs : 0) * BS + (r < BS ? r : 0)) * n;
-    double2 s2, is2, s2lo, s2hi;
-    strip_profile(P, kind, j0, dir, r < BS ? r : 0, s2, is2, s2lo, s2hi);
-    strip_solve<T, TF, BS, RP>(P, fac, is2, spill + (int64_t)blockIdx.x * n * 64, zx,
-        [&](int i) { return act ? ccast<T, double>(g[off + i - 1]) : mk<T>(0, 0); },
-        [&](int i, C2<T> v) { if (act) x[off + i - 1] = cvt_out<double2, T>(v); });
+    const int T1 = n + 1;
+    const int nticks = (m + 2) * T1;
+
+    // Prefetch cursor (pair pi, tick pk), D ticks ahead of execution.  Loads are unconditional:
+    // positions past the end are clamped to valid memory and their values are never used, so each
+    // tick issues the same load sequence and the compiler waits on exactly the loads issued D ticks
+    // earlier.  Strip-dependent bases are recomputed only when the cursor enters a new pair.
+    int pi = 0, pk = 0, pdir = 1;
+    const HS_GLOBAL char* pfb = facbase;         // backward strip pi-1
+    const HS_GLOBAL char* pff = facbase;         // forward strip pi
+    const HS_GLOBAL C2<T>* pspb = spill;         // workspace of strip pi-1
+    const HS_GLOBAL TI* pfrow = fin;             // MODE_FWD: input row of strip pi
+    const HS_GLOBAL TO* pyrow = y;               // MODE_BWD: output row of strip pi-1
+    auto pset = [&]() __attribute__((always_inline)) {
+        const int pc = pi <= m + 1 ? pi : m + 1;
+        const int ib = pc >= 1 ? pc - 1 : 0, ifw = pc <= m ? pc : m;
+        pdir = strip_dir(pc);
+        pfb = strip_fac(ib);
+        pff = strip_fac(ifw);
+        pspb = spill + (int64_t)(ib & 1) * n * 64 + lane;
+        if (MODE == MODE_FWD) pfrow = fin + (int64_t)(strip_row(ifw, strip_full(ifw)) - 1) * n;
+        if (MODE == MODE_BWD) pyrow = y + (int64_t)(strip_row(ib, strip_full(ib)) - 1) * n;
+    };
+    pset();
+    auto prefetch = [&](chunk16 (&bk)[NCH], chunk16 (&fk)[NCH], CT& sp, double2& a0, double2& a1,
+                        double2& a2) __attribute__((always_inline)) {
+        const int k2 = pk < n ? pk : n - 1;
+        const int col = pdir > 0 ? k2 + 1 : n - k2;
+        const HS_GLOBAL chunk16* srcb = (const HS_GLOBAL chunk16*)(pfb + (int64_t)(sizeof(CF) * STRIDE) * (n - 1 - k2));
+        const HS_GLOBAL chunk16* srcf = (const HS_GLOBAL chunk16*)(pff + (int64_t)(sizeof(CF) * STRIDE) * k2);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
+            bk[c] = srcb[idx];
+            fk[c] = srcf[idx];
+        }
+        sp = gld(pspb + (int64_t)(n - 1 - k2) * 64);
+        if (MODE == MODE_FWD) {
+            a0 = ld2(pfrow + col - 1);
+        } else if (MODE == MODE_BWD) {
+            a0 = ld2(y + (int64_t)(cmid - 1) * n + col - 1);
+            a1 = ld2(pyrow + col - 1);
+        } else if (MODE == MODE_MID) {
+            a0 = ld2(fin + (int64_t)(cmid - 1) * n + col - 1);
+            a1 = ld2(y + (int64_t)(cmid - 2) * n + col - 1);
+            a2 = ld2(y + (int64_t)cmid * n + col - 1);
+        } else {
+            a0 = gld(sag + ((int64_t)rhs * BS + rr) * n + col - 1);
+        }
+        if (++pk == T1) { pk = 0; ++pi; pset(); }
+    };
+
+    // Lambda^{-1} row r of a staged column (packed upper triangle) times the exchange vector of group q:
+    // element offsets of this lane's row entries k = kg + KS j are computed once
+    int loff[KMAX];
+#pragma unroll
+    for (int jj = 0; jj < KMAX; ++jj) {
+        const int k = kg + KS * jj < BS ? kg + KS * jj : BS - 1;
+        loff[jj] = (k >= rr) ? (rr * BS - (rr * (rr - 1)) / 2 + (k - rr)) : (k * BS - (k * (k - 1)) / 2 + (rr - k));
+    }
+    auto rowdot = [&](const chunk16* colv, const CT (*xv)[RP]) __attribute__((always_inline)) -> CT {
+        const CF* cf = (const CF*)colv;
+        CT acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
+#pragma unroll
+        for (int jj = 0; jj < KMAX; ++jj) {
+            const int k = kg + KS * jj;                   // k >= BS only in the last round of a k-split
+            const CT l = ccast<T, TF>(cf[loff[jj]]);
+            const CT xk = xv[q][KS == 1 ? jj : (k < BS ? k : 0)];
+            const CT t = (KS == 1 || k < BS) ? xk : mk<T>(0, 0);
+            if (jj & 1) acc1 = cfma<T>(l, t, acc1);
+            else acc0 = cfma<T>(l, t, acc0);
+        }
+        CT acc = cadd<T>(acc0, acc1);
+#pragma unroll
+        for (int off = RP; off < RP * KS; off <<= 1) {
+            acc.x += __shfl_xor(acc.x, off);
+            acc.y += __shfl_xor(acc.y, off);
+        }
+        return acc;
+    };
+    auto colscalar = [&](const chunk16* colv, int which) __attribute__((always_inline)) -> CT {
+        return ccast<T, TF>(((const CF*)colv)[PACK + which]);
+    };
+
+    static_for<D>([&](auto UC) __attribute__((always_inline)) {
+        constexpr int u = decltype(UC)::value;
+        prefetch(rbk[u], rfk[u], rsp[u], ra[u], rb2[u], rc[u]);
+    });
+
+    bool full_b = false, full_f = false;
+    int row_b = 1, row_f = 1;
+    CT is2b = mk<T>(0, 0), is2f = mk<T>(0, 0);
+    CT xcur = mk<T>(0, 0), z = mk<T>(0, 0), w = mk<T>(0, 0), wcarry = mk<T>(0, 0), ypart = mk<T>(0, 0);
+    CT wlag[LAG], wsnap[LAG];
+#pragma unroll
+    for (int j = 0; j < LAG; ++j) { wlag[j] = mk<T>(0, 0); wsnap[j] = mk<T>(0, 0); }
+
+    int i = 0, k = 0;                                   // execution cursor: pair i, tick k
+    for (int K0 = 0; K0 < nticks; K0 += D) {
+        static_for<D>([&](auto UC) __attribute__((always_inline)) {
+            constexpr int u = decltype(UC)::value;
+            const int K = K0 + u;
+            if (K < nticks) {
+                if (k == 0) {
+                    const int ib = i >= 1 ? i - 1 : 0, ifw = i <= m ? i : m;
+                    full_b = strip_full(ib); row_b = strip_row(ib, full_b); is2b = strip_is2(ib);
+                    full_f = strip_full(ifw); row_f = strip_row(ifw, full_f); is2f = strip_is2(ifw);
+                }
+                const bool bon = i >= 1 && k < n;
+                const bool fon = i <= m && k >= 1;
+                const bool fin_on = i <= m && k < n;
+                const int col = colof(strip_dir(i), k);
+                // stage the columns of this tick and the exchange vectors
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int idx = c * 64 + lane;
+                    if (idx < N16) { colb[idx] = rbk[u][c]; colf[k & 1][idx] = rfk[u][c]; }
+                }
+                xbx[q][r] = cmul<T>(is2b, xcur);
+                xfx[q][r] = z;
+                __syncthreads();
+                // backward pass of strip i-1, step s = n-1-k
+                CT ws = rsp[u];
+#pragma unroll
+                for (int j = 0; j < LAG; ++j) ws = (k == j + 1) ? wsnap[j] : ws;
+                const CT xb = cfms<T>(colscalar(colb, XCOL_E), rowdot(colb, xbx), ws);
+                // forward pass of strip i: product for step k-1
+                const chunk16* cprev = colf[(k + 1) & 1];
+                const CT wf = rowdot(cprev, xfx);
+                if (bon) {
+                    const CT x = k == 0 ? wcarry : xb;
+                    xcur = x;
+                    if (MODE == MODE_FWD) {
+                        if (full_b ? own : oslot) gst(y + (int64_t)(row_b - 1) * n + col - 1, cvt_out<TO, T>(x));
+                        ypart = x;
+                    } else if (MODE == MODE_BWD) {
+                        const CT yn = csub<T>(ccast<T, double>(rb2[u]), x);
+                        if (full_b ? own : oslot) gst(y + (int64_t)(row_b - 1) * n + col - 1, cvt_out<TO, T>(yn));
+                        ypart = yn;
+                    } else if (MODE == MODE_MID) {
+                        if (oslot) gst(y + (int64_t)(cmid - 1) * n + col - 1, cvt_out<TO, T>(x));
+                    } else {
+                        if (own) gst(sax + ((int64_t)rhs * BS + r) * n + col - 1, cvt_out<double2, T>(x));
+                    }
+                }
+                if (fon) {
+#pragma unroll
+                    for (int j = LAG - 1; j >= 1; --j) wlag[j] = wlag[j - 1];
+                    wlag[0] = w;
+                    w = wf;
+                    gst(spill + (int64_t)(i & 1) * n * 64 + (int64_t)(k - 1) * 64 + lane, w);
+                    if (k == n) {
+                        wcarry = w;
+#pragma unroll
+                        for (int j = 0; j < LAG; ++j) wsnap[j] = wlag[j];
+                    }
+                }
+                if (fin_on) {
+                    const chunk16* cc = colf[k & 1];
+                    CT g = mk<T>(0, 0);
+                    if (MODE == MODE_FWD) {
+                        double2 gv = ra[u];
+                        if (!full_f) gv = csub<double>(gv, ccast<double, T>(cmul<T>(colscalar(cc, XCOL_APREV), ypart)));
+                        g = (full_f ? act : slot) ? ccast<T, double>(gv) : mk<T>(0, 0);
+                    } else if (MODE == MODE_BWD) {
+                        g = slot ? cmul<T>(colscalar(cc, XCOL_ANEXT), i == 0 ? ccast<T, double>(ra[u]) : ypart) : mk<T>(0, 0);
+                    } else if (MODE == MODE_MID) {
+                        double2 gv = ra[u];
+                        gv = csub<double>(gv, cmul<double>(ccast<double, T>(colscalar(cc, XCOL_APREV)), rb2[u]));
+                        gv = csub<double>(gv, cmul<double>(ccast<double, T>(colscalar(cc, XCOL_ANEXT)), rc[u]));
+                        g = slot ? ccast<T, double>(gv) : mk<T>(0, 0);
+                    } else {
+                        g = act ? ccast<T, double>(ra[u]) : mk<T>(0, 0);
+                    }
+                    z = k == 0 ? g : cfms<T>(cmul<T>(colscalar(cprev, XCOL_E), is2f), w, g);
+                }
+                prefetch(rbk[u], rfk[u], rsp[u], ra[u], rb2[u], rc[u]);
+                if (++k == T1) { k = 0; ++i; }
+            }
+        });
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------------------------
-template <class T, class TF, class TI, class TO>
-static bool chains_typed(int B, int phase, const ProbDev* probs, const ChainDev* chains, int nch, const IoDev* io,
-                         IoDev iov, void* spill, hipStream_t s) {
-    dim3 g(nch), b(64);
+// prefetch distance in ticks: as deep as the register budget of one wave allows
+template <class T, int BS> struct Ring { static constexpr int D = (sizeof(T) == 8 || BS > 17) ? 2 : 4; };
+
+template <class T, class TF, class TI, class TO, int MODE>
+static bool sweep_typed(int bs, int ks, const ProbDev* probs, const ChainDev* chains, int nblocks, const IoDev* io,
+                        IoDev iov, void* spill, const SubArg& sa, hipStream_t s) {
+    dim3 g(nblocks), b(64);
     C2<T>* sp = (C2<T>*)spill;
-    switch (B) {
-#define HS_CASE(BV) case BV: hipLaunchKernelGGL((k_chain<T, TF, TI, TO, BV>), g, b, 0, s, probs, chains, io, iov, phase, sp); return true;
-        HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13) HS_CASE(17)
-#undef HS_CASE
-        default: return false;
-    }
-}
-
-template <class T, class TF, class TI, class TO>
-static bool middle_typed(int B, const ProbDev* probs, const ChainDev* mids, int nm, const IoDev* io, IoDev iov,
-                         void* spill, hipStream_t s) {
-    dim3 g(nm), b(64);
-    C2<T>* sp = (C2<T>*)spill;
-    switch (2 * B - 1) {
-#define HS_CASE(BV) case BV: hipLaunchKernelGGL((k_middle<T, TF, TI, TO, BV>), g, b, 0, s, probs, mids, io, iov, sp); return true;
-        HS_CASE(7) HS_CASE(9) HS_CASE(13) HS_CASE(17) HS_CASE(25) HS_CASE(33)
-#undef HS_CASE
-        default: return false;
-    }
-}
-
-bool launch_chains(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
-                   const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
-    if (nchains <= 0) return true;
-    if (prec == 0) {
-        if (in_prec == 0 && out_prec == 0) return chains_typed<double, double, double2, double2>(B, phase, probs, chains, nchains, io, io_val, spill, s);
-        return false;
-    }
-    if (in_prec == 0 && out_prec == 1) return chains_typed<float, float, double2, float2>(B, phase, probs, chains, nchains, io, io_val, spill, s);
-    if (in_prec == 1 && out_prec == 1) return chains_typed<float, float, float2, float2>(B, phase, probs, chains, nchains, io, io_val, spill, s);
-    if (in_prec == 0 && out_prec == 0) return chains_typed<float, float, double2, double2>(B, phase, probs, chains, nchains, io, io_val, spill, s);
-    return false;
-}
-
-bool launch_middle(int B, int prec, int in_prec, int out_prec, const ProbDev* probs, const ChainDev* mids,
-                   int nmids, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
-    if (nmids <= 0) return true;
-    if (prec == 0) {
-        if (in_prec == 0 && out_prec == 0) return middle_typed<double, double, double2, double2>(B, probs, mids, nmids, io, io_val, spill, s);
-        return false;
-    }
-    if (in_prec == 0 && out_prec == 1) return middle_typed<float, float, double2, float2>(B, probs, mids, nmids, io, io_val, spill, s);
-    if (in_prec == 1 && out_prec == 1) return middle_typed<float, float, float2, float2>(B, probs, mids, nmids, io, io_val, spill, s);
-    if (in_prec == 0 && out_prec == 0) return middle_typed<float, float, double2, double2>(B, probs, mids, nmids, io, io_val, spill, s);
-    return false;
-}
-
-int chain_padded_rows(int B) { return B <= 16 ? 16 : (B <= 32 ? 32 : 64); }
-int chain_rhs_per_wave(int B) { return 64 / chain_padded_rows(B); }
-int middle_rhs_per_wave(int B) { return 64 / chain_padded_rows(2 * B - 1); }
-
-template <class T, class TF>
-static bool subsolve_typed(int bs, const ProbDev* prob, const void* fac, int kind, int j0, int dir, const void* g,
-                           void* x, int nrhs, void* spill, hipStream_t s) {
-    const int Q = 64 / chain_padded_rows(bs);
-    dim3 gr((nrhs + Q - 1) / Q), b(64);
     switch (bs) {
-#define HS_CASE(BV) case BV: hipLaunchKernelGGL((k_subsolve<T, TF, BV>), gr, b, 0, s, prob, (const C2<TF>*)fac, kind, j0, dir, \
-                                                (const double2*)g, (double2*)x, nrhs, (C2<T>*)spill); return true;
+#define HS_CASE(BV)                                                                                               \
+    case BV:                                                                                                      \
+        if (ks == 1)                                                                                              \
+            hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, Ring<T, BV>::D, 1>), g, b, 0, s, probs, chains, io, \
+                               iov, sp, sa);                                                                      \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, Ring<T, BV>::D, RowsOf<BV>::Q>), g, b, 0, s, probs,  \
+                               chains, io, iov, sp, sa);                                                          \
+        return true;
         HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13) HS_CASE(17) HS_CASE(25) HS_CASE(33)
 #undef HS_CASE
         default: return false;
     }
 }
 
-bool launch_subsolve(int bs, int prec, const ProbDev* prob, const void* fac, int kind, int j0, int dir,
-                     const void* g, void* x, int nrhs, void* spill, hipStream_t s) {
-    return prec == 0 ? subsolve_typed<double, double>(bs, prob, fac, kind, j0, dir, g, x, nrhs, spill, s)
-                     : subsolve_typed<float, float>(bs, prob, fac, kind, j0, dir, g, x, nrhs, spill, s);
+template <int MODE>
+static bool sweep_prec(int bs, int ks, int prec, int in_prec, int out_prec, const ProbDev* probs, const ChainDev* chains,
+                       int nb, const IoDev* io, IoDev iov, void* spill, const SubArg& sa, hipStream_t s) {
+    if (prec == 0) {
+        if (in_prec == 0 && out_prec == 0)
+            return sweep_typed<double, double, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, sa, s);
+        return false;
+    }
+    if (in_prec == 0 && out_prec == 1)
+        return sweep_typed<float, float, double2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, sa, s);
+    if (in_prec == 1 && out_prec == 1)
+        return sweep_typed<float, float, float2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, sa, s);
+    return false;
+}
+
+bool launch_chains(int B, int prec, int in_prec, int out_prec, int phase, int ksplit, const ProbDev* probs,
+                   const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
+    if (nchains <= 0) return true;
+    SubArg sa{};
+    return phase == 0
+               ? sweep_prec<MODE_FWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, spill, sa, s)
+               : sweep_prec<MODE_BWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, spill, sa, s);
+}
+
+bool launch_middle(int B, int prec, int in_prec, int out_prec, int ksplit, const ProbDev* probs, const ChainDev* mids,
+                   int nmids, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
+    if (nmids <= 0) return true;
+    SubArg sa{};
+    return sweep_prec<MODE_MID>(2 * B - 1, ksplit, prec, in_prec, out_prec, probs, mids, nmids, io, io_val, spill, sa, s);
+}
+
+int chain_padded_rows(int B) { return B <= 16 ? 16 : (B <= 32 ? 32 : 64); }
+int chain_rhs_per_wave(int B) { return 64 / chain_padded_rows(B); }
+int middle_rhs_per_wave(int B) { return 64 / chain_padded_rows(2 * B - 1); }
+
+bool launch_subsolve(int bs, int prec, const ProbDev* prob, const void* fac, const double2* ris2, int rstep, int cdir,
+                     int jl, const void* g, void* x, int nrhs, void* spill, hipStream_t s) {
+    const int Q = 64 / chain_padded_rows(bs);      // no k-split: one right-hand side per row group
+    SubArg sa{fac, (const double2*)g, (double2*)x, ris2, nrhs, rstep, cdir, jl};
+    IoDev none{nullptr, nullptr, nullptr};
+    const int nb = (nrhs + Q - 1) / Q;
+    if (prec == 0) return sweep_typed<double, double, double2, double2, MODE_SUB>(bs, 1, prob, nullptr, nb, nullptr, none, spill, sa, s);
+    return sweep_typed<float, float, double2, double2, MODE_SUB>(bs, 1, prob, nullptr, nb, nullptr, none, spill, sa, s);
 }
 
 }  // namespace hs

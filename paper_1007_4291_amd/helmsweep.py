@@ -25,10 +25,11 @@ HELM_C128 = 0
 HELM_C64 = 1
 
 # every symbol the header declares
-EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_problem_n", "helm_matvec", "sweep_factor",
-           "sweep_factor_bytes", "sweep_apply", "sweep_subsolve", "sweep_num_subproblems", "sweep_subproblem_rows",
+EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_reassemble", "helm_problem_n", "helm_matvec",
+           "sweep_factor", "sweep_refactor", "sweep_factor_bytes", "sweep_apply", "sweep_subsolve", "sweep_num_subproblems", "sweep_subproblem_rows",
            "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "helm_free", "sweep_free",
-           "helm_batch_free"]
+           "helm_batch_free", "helm_timing_enable", "helm_timing_read"]
+PHASES = ["assemble", "factor", "sweep_fwd", "sweep_mid", "sweep_bwd", "matvec", "krylov"]
 
 
 class HelmError(RuntimeError):
@@ -51,9 +52,11 @@ def _load() -> C.CDLL:
         "helm_version": (C.c_char_p, []),
         "helm_last_error": (C.c_char_p, []),
         "helm_assemble": (C.c_int, [C.POINTER(HelmParams), vp, vp, C.POINTER(vp)]),
+        "helm_reassemble": (C.c_int, [vp, vp, vp]),
         "helm_problem_n": (C.c_int, [vp]),
         "helm_matvec": (C.c_int, [vp, vp, i32, vp, i32, vp]),
         "sweep_factor": (C.c_int, [vp, i32, vp, C.POINTER(vp)]),
+        "sweep_refactor": (C.c_int, [vp, vp]),
         "sweep_factor_bytes": (C.c_int64, [vp]),
         "sweep_apply": (C.c_int, [vp, vp, vp, i32, i32, vp]),
         "sweep_subsolve": (C.c_int, [vp, i32, vp, vp, i32, vp]),
@@ -66,6 +69,8 @@ def _load() -> C.CDLL:
         "helm_free": (None, [vp]),
         "sweep_free": (None, [vp]),
         "helm_batch_free": (None, [vp]),
+        "helm_timing_enable": (C.c_int, [i32]),
+        "helm_timing_read": (C.c_int, [C.POINTER(f64), C.POINTER(C.c_int64), i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -159,6 +164,14 @@ class Problem:
     def handle(self):
         return self._h
 
+    def reassemble(self, c, stream=None):
+        """Recompute the tables in place from a new velocity (a1, no allocation)."""
+        torch = _torch()
+        if not (isinstance(c, torch.Tensor) and c.is_cuda and c.dtype == torch.float64 and c.is_contiguous()
+                and c.numel() == self.N):
+            raise ValueError("c must be a contiguous float64 device tensor with n*n values")
+        _check(_lib.helm_reassemble(self._h, C.c_void_p(c.data_ptr()), C.c_void_p(_stream(stream))))
+
     def matvec(self, x, y=None, stream=None):
         """y = A x (FP64, eq. helmd); x complex128 or complex64 [nrhs, N] or [N]."""
         torch = _torch()
@@ -193,6 +206,10 @@ class Factors:
     @property
     def handle(self):
         return self._h
+
+    def refactor(self, stream=None):
+        """Recompute every strip factor in place (a2, no allocation)."""
+        _check(_lib.sweep_refactor(self._h, C.c_void_p(_stream(stream))))
 
     @property
     def nbytes(self) -> int:
@@ -238,6 +255,19 @@ class Factors:
         if h is not None and h.value:
             _lib.sweep_free(h)
             self._h = None
+
+
+def timing_enable(on: bool = True):
+    """Record HIP events around every kernel group (per phase)."""
+    _check(_lib.helm_timing_enable(1 if on else 0))
+
+
+def timing_read(reset: bool = True):
+    """{phase: (milliseconds, launches)} summed since the last reset."""
+    ms = (C.c_double * 7)()
+    ln = (C.c_int64 * 7)()
+    _check(_lib.helm_timing_read(ms, ln, 1 if reset else 0))
+    return {PHASES[i]: (ms[i], int(ln[i])) for i in range(7)}
 
 
 @dataclass
