@@ -78,8 +78,7 @@ class Runner:
     def step(self):
         for A, c in zip(self.A, self.c):
             A.reassemble(c)
-        for M in self.M:
-            M.refactor()
+        self.batch.refactor()
         for u in self.u:
             u.zero_()
         self.last = self.batch.solve(self.f, self.u, tol=self.tol, maxit=400)

@@ -155,6 +155,13 @@ int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* const* u, dou
  * complex128). */
 int sweep_apply_batch(helm_batch_t b, const void* const* f, void* const* u, void* stream);
 
+/* a2 for the whole batch (Algorithm 3 for every problem): recompute the factors of every member
+ * from its problem's current tables, all height-B strips of all problems in one launch and the
+ * middle strips in a second one that overlaps it.  Equivalent to sweep_refactor on each member;
+ * allocates nothing.  Returns HELM_ESINGULAR naming the first problem with a zero or non-finite
+ * pivot.  Synchronises `stream`. */
+int sweep_refactor_batch(helm_batch_t b, void* stream);
+
 /* Per-phase kernel timing with HIP events recorded on the launch stream around every kernel
  * group (process-wide; off by default).  Phases: 0 assemble, 1 factor, 2 sweep forward chains,
  * 3 sweep middle layer, 4 sweep backward chains, 5 matvec, 6 Krylov vector kernels.

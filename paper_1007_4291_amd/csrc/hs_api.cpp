@@ -154,6 +154,17 @@ struct helm_batch_s {
     DevBuf H, cs, g, y, partial, hbuf, nrm, inv, est, fnorm, beta, active, cnt;
     std::vector<int64_t> voff, zoff, woff;   // element offsets of each problem's blocks
     size_t zelem = 16;
+    // batched refactorisation: strip tables of all problems (height B, and the middles) and a
+    // second stream so that the two launches overlap
+    DevBuf fsubs, msubs, fstatus;
+    int nfsubs = 0, nmsubs = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    ~helm_batch_s() {
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
+    }
 };
 
 sweep_factors_s::~sweep_factors_s() {
@@ -275,19 +286,20 @@ static int factor_into(sweep_factors_t M, hipStream_t s) {
     const int n = A->n, B = A->B;
     HIPCHK(hipMemsetAsync(M->status.p, 0, sizeof(int), s));
     const ProbDev* pd = A->pd.as<ProbDev>();
+    (void)n;
     {
         PhaseScope ph(PH_FACTOR, s, 2);
-        if (!launch_factor(B, M->prec, pd, M->subs.as<SubDev>(), A->nsub - 1, n, M->fac.p, M->status.as<int>(), s))
+        if (!launch_factor(B, M->prec, pd, M->subs.as<SubDev>(), A->nsub - 1, M->status.as<int>(), s))
             return fail(HELM_EINVAL, "no factor kernel for B=%d", B);
         LAUNCHCHK();
-        if (!launch_factor(2 * B - 1, M->prec, pd, M->subs.as<SubDev>() + (A->nsub - 1), 1, n, M->fac.p,
-                           M->status.as<int>(), s))
+        if (!launch_factor(2 * B - 1, M->prec, pd, M->subs.as<SubDev>() + (A->nsub - 1), 1, M->status.as<int>(), s))
             return fail(HELM_EINVAL, "no factor kernel for middle height %d", 2 * B - 1);
         LAUNCHCHK();
     }
     int st = 0;
     HIPCHK(hipMemcpyAsync(&st, M->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (st & 2) return fail(HELM_EINVAL, "internal: strips of different sizes in one factor workgroup");
     if (st) return fail(HELM_ESINGULAR, "zero or non-finite pivot while inverting a diagonal block");
     return HELM_OK;
 }
@@ -338,6 +350,7 @@ extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_
         } else {
             d.rs2 = P.mdn; d.ris2 = P.imdn; d.rlo = P.mdh; d.rhi = P.mdh + 1; d.rstep = 1;
         }
+        d.facp = (char*)M->fac.p + esz * d.fac_off;
     }
     M->sub_rows.assign(S.size(), B);
     M->sub_rows.back() = 2 * B - 1;
@@ -510,6 +523,37 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
     for (int p = 0; p < count; ++p) pdv.push_back(A[p]->host);
     if ((rc = b->probs.alloc(sizeof(ProbDev) * count))) return rc;
     HIPCHK(hipMemcpy(b->probs.p, pdv.data(), sizeof(ProbDev) * count, hipMemcpyHostToDevice));
+    // strip tables for the batched refactorisation (largest problems first)
+    {
+        std::vector<int> ord(count);
+        for (int p = 0; p < count; ++p) ord[p] = p;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return A[a]->n > A[c]->n; });
+        // One factor workgroup holds Q strips that must share n: strips are ordered by n and each
+        // run of equal n is padded to whole workgroups with entries that store nothing.
+        std::vector<SubDev> fs, ms;
+        const int qf = 64 / chain_padded_rows(B), qm = 64 / chain_padded_rows(2 * B - 1);
+        auto pad = [](std::vector<SubDev>& v, int q) {
+            while (v.size() % q) { v.push_back(v.back()); v.back().facp = nullptr; }
+        };
+        for (size_t t = 0; t < ord.size(); ++t) {
+            const int p = ord[t];
+            const std::vector<SubDev>& hs = M[p]->hsubs;
+            for (size_t u = 0; u + 1 < hs.size(); ++u) { fs.push_back(hs[u]); fs.back().prob = p; }
+            ms.push_back(hs.back());
+            ms.back().prob = p;
+            if (t + 1 == ord.size() || A[ord[t + 1]]->n != A[p]->n) { pad(fs, qf); pad(ms, qm); }
+        }
+        b->nfsubs = (int)fs.size();
+        b->nmsubs = (int)ms.size();
+        if ((rc = b->fsubs.alloc(sizeof(SubDev) * fs.size()))) return rc;
+        if ((rc = b->msubs.alloc(sizeof(SubDev) * ms.size()))) return rc;
+        if ((rc = b->fstatus.alloc(sizeof(int) * count))) return rc;
+        HIPCHK(hipMemcpy(b->fsubs.p, fs.data(), sizeof(SubDev) * fs.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->msubs.p, ms.data(), sizeof(SubDev) * ms.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    }
     // chains (longest first), middles
     int Q, Qm;
     rhs_grouping(B, *std::max_element(b->nrhs.begin(), b->nrhs.end()), &Q, &b->ks_chain, &Qm, &b->ks_mid);
@@ -589,6 +633,36 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
     if ((rc = b->cnt.alloc(sizeof(int32_t) * ns))) return rc;
     (void)s;
     *out = b.release();
+    return HELM_OK;
+}
+
+extern "C" int sweep_refactor_batch(helm_batch_t b, void* stream) {
+    if (!b) return fail(HELM_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int B = b->B;
+    HIPCHK(hipMemsetAsync(b->fstatus.p, 0, sizeof(int) * b->count, s));
+    {
+        PhaseScope ph(PH_FACTOR, s, 2);
+        // middles (few, long) on the side stream, overlapping the many height-B strips
+        HIPCHK(hipEventRecord(b->ev_fork, s));
+        HIPCHK(hipStreamWaitEvent(b->side, b->ev_fork, 0));
+        if (!launch_factor(2 * B - 1, b->prec, b->probs.as<ProbDev>(), b->msubs.as<SubDev>(), b->nmsubs,
+                           b->fstatus.as<int>(), b->side))
+            return fail(HELM_EINVAL, "no factor kernel for middle height %d", 2 * B - 1);
+        LAUNCHCHK();
+        HIPCHK(hipEventRecord(b->ev_join, b->side));
+        if (!launch_factor(B, b->prec, b->probs.as<ProbDev>(), b->fsubs.as<SubDev>(), b->nfsubs, b->fstatus.as<int>(), s))
+            return fail(HELM_EINVAL, "no factor kernel for B=%d", B);
+        LAUNCHCHK();
+        HIPCHK(hipStreamWaitEvent(s, b->ev_join, 0));
+    }
+    std::vector<int> st(b->count, 0);
+    HIPCHK(hipMemcpyAsync(st.data(), b->fstatus.p, sizeof(int) * b->count, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int p = 0; p < b->count; ++p) {
+        if (st[p] & 2) return fail(HELM_EINVAL, "internal: strips of different sizes in one factor workgroup");
+        if (st[p]) return fail(HELM_ESINGULAR, "problem %d: zero or non-finite pivot while inverting a diagonal block", p);
+    }
     return HELM_OK;
 }
 

@@ -82,6 +82,15 @@ __device__ __forceinline__ void gst(HS_GLOBAL float2* p, float2 v) {
     *(HS_GLOBAL hs_f2v*)p = w;
 }
 
+// Ordering of LDS accesses inside a workgroup of exactly one wave.  LDS operations of one wave are
+// performed in issue order, so only the compiler has to be kept from moving memory accesses across
+// this point; unlike __syncthreads() it does not wait for outstanding global loads.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------------------------
 // descriptors
 // ---------------------------------------------------------------------------------------------
@@ -110,7 +119,8 @@ struct SubDev {
     int32_t jl;         // layer row of the strip (the row whose values leave the strip)
     int32_t jprev;      // layer row of the previous layer in the sweep (0: none)
     int32_t jnext;      // layer row of the next layer in the sweep (0: none)
-    int64_t fac_off;    // offset of this strip's factor (in complex elements)
+    int64_t fac_off;    // offset of this strip's factor in its problem's store (complex elements)
+    void* facp;         // absolute address of the strip's first stored column
     // The strip's x2 profile resolved on the host (no branch on the strip kind in device code):
     // local row r has s2 = rs2[rstep*r], 1/s2 = ris2[rstep*r], and s2 at the half rows below and
     // above it rlo[rstep*r], rhi[rstep*r].

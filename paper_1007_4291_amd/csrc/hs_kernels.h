@@ -46,8 +46,9 @@ int matvec_blocks(int n);
 // a2: factor `nsub` strips of height `bs` (all of one problem). prec 0: complex128 store,
 // 1: complex64 store.  status: device int, bit 0 set on a zero / non-finite pivot.
 // Returns false if `bs` has no compiled instance.
-bool launch_factor(int bs, int prec, const ProbDev* prob, const SubDev* subs, int nsub, int n,
-                   void* fac, int* status, hipStream_t s);
+// One launch over nsub strips of height bs (each SubDev names its problem and factor address);
+// status[prob] is or-ed with 1 when a pivot of that problem is zero or not finite.
+bool launch_factor(int bs, int prec, const ProbDev* probs, const SubDev* subs, int nsub, int* status, hipStream_t s);
 
 // a3/a4: sweep chains and middle layer.
 //   phase 0: forward substitution + diagonal applications along each chain

@@ -290,7 +290,7 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
                 }
                 xbx[q][r] = cmul<T>(is2b, xcur);
                 xfx[q][r] = z;
-                __syncthreads();
+                wave_sync();
                 // backward pass of strip i-1, step s = n-1-k
                 CT ws = rsp[u];
 #pragma unroll

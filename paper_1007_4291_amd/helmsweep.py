@@ -27,7 +27,8 @@ HELM_C64 = 1
 # every symbol the header declares
 EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_reassemble", "helm_problem_n", "helm_matvec",
            "sweep_factor", "sweep_refactor", "sweep_factor_bytes", "sweep_apply", "sweep_subsolve", "sweep_num_subproblems", "sweep_subproblem_rows",
-           "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "helm_free", "sweep_free",
+           "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "sweep_refactor_batch",
+           "helm_free", "sweep_free",
            "helm_batch_free", "helm_timing_enable", "helm_timing_read"]
 PHASES = ["assemble", "factor", "sweep_fwd", "sweep_mid", "sweep_bwd", "matvec", "krylov"]
 
@@ -66,6 +67,7 @@ def _load() -> C.CDLL:
         "helm_batch_create": (C.c_int, [C.POINTER(vp), C.POINTER(vp), C.POINTER(i32), i32, i32, vp, C.POINTER(vp)]),
         "fgmres_solve_batch": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), f64, i32, C.POINTER(i32), C.POINTER(f64), vp]),
         "sweep_apply_batch": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), vp]),
+        "sweep_refactor_batch": (C.c_int, [vp, vp]),
         "helm_free": (None, [vp]),
         "sweep_free": (None, [vp]),
         "helm_batch_free": (None, [vp]),
@@ -333,6 +335,10 @@ class Batch:
         rc = _lib.fgmres_solve_batch(self._h, fp, up, tol, maxit, it, rr, C.c_void_p(_stream(stream)))
         _check(rc, allow_notconv=True)
         return SolveResult(u, list(it), list(rr), rc == HELM_OK)
+
+    def refactor(self, stream=None):
+        """Recompute the factors of every member in place (a2 over the whole batch, two launches)."""
+        _check(_lib.sweep_refactor_batch(self._h, C.c_void_p(_stream(stream))))
 
     def apply(self, f: Sequence, u: Optional[Sequence] = None, stream=None):
         torch = _torch()

@@ -262,3 +262,33 @@ def test_error_paths_on_gpu(hs, torch):
     assert not res.converged and res.iters == [1] and res.relres[0] > 1e-10
     with pytest.raises(hs.HelmError):
         hs.fgmres(A, F, f, tol=2.0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_refactor_equals_individual(hs, torch, prec):
+    """sweep_refactor_batch (all strips of all problems in two launches) writes the same factors as
+    factoring each problem on its own: the applies agree bit for bit."""
+    specs = [(47, 2), (63, 1), (39, 3)]
+    probs, facs, fs, ref, cs = [], [], [], [], []
+    for n, R in specs:
+        op = OH.Params(n=n, omega=2 * math.pi * n / 8, alpha=2.0, pml_w=8, mpml_w=8)
+        c = workloads.velocity_layered(n, seed=n)
+        A = _gpu_problem(hs, torch, op, c)
+        F = hs.Factors(A, prec)
+        f = torch.as_tensor(workloads.random_rhs(n, R, seed=n + 2), device="cuda")
+        if prec == hs.HELM_C64:   # complex64 factors take complex64 vectors
+            f = f.to(torch.complex64)
+        ref.append(F.apply(f).cpu().numpy())
+        probs.append(A); facs.append(F); fs.append(f)
+        cs.append(torch.as_tensor(c, dtype=torch.float64, device="cuda"))
+    b = hs.Batch(probs, facs, [R for _, R in specs], restart=5)
+    # leave every store holding the factors of another velocity, then restore the tables only:
+    # the batched pass has to rewrite every column for the applies to match
+    for A, F, c in zip(probs, facs, cs):
+        A.reassemble((c * 1.25).contiguous())
+        F.refactor()
+        A.reassemble(c)
+    b.refactor()
+    for F, f, u0 in zip(facs, fs, ref):
+        u = F.apply(f).cpu().numpy()
+        assert np.array_equal(u, u0)
