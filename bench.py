@@ -128,6 +128,27 @@ def sweep_bytes_flops(probs, B, fac_bytes, vin, vout):
     return b0, b1, fl
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_chains_batched96_c64_traffic.json")
+TRAFFIC_SOURCES = ["paper_1007_4291_amd/csrc/hs_sweep.hip", "paper_1007_4291_amd/csrc/hs_common.h",
+                   "paper_1007_4291_amd/csrc/hs_kernels.h", "paper_1007_4291_amd/csrc/hs_api.cpp"]
+
+
+def measured_traffic(workload, prec_name):
+    """HBM bytes per chain launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by
+    the copy-kernel calibration), or None when they do not describe this workload or when the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    if workload != "batched" or prec_name != "c64" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        tr = json.load(fh)
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return tr["traffic_bytes_per_launch"] if h.hexdigest() == tr.get("source_sha256") else None
+
+
 def cpu_baseline(probs):
     """The oracle, untuned, on a bounded sample: one problem of the workload, all its right-hand sides."""
     import numpy as np
@@ -187,9 +208,10 @@ def main():
     avg_ms = (ms_f + ms_b) / max(1, n_f + n_b)
     bytes_per_launch = (b0 + b1) / 2
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(a.workload, a.prec)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-            "kernel": "k_chain (sweep forward/backward chains)", "avg_launch_ms": round(avg_ms, 4),
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": int(traffic) if traffic else None,
+            "kernel": "k_sweep forward/backward chain launches", "avg_launch_ms": round(avg_ms, 4),
             "launches": n_f + n_b, "algorithmic_bytes_per_launch": int(bytes_per_launch),
             "tflops": round(fl / (avg_ms * 1e-3) / 1e12, 4)}
 

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -382,10 +383,24 @@ static size_t compute_elem(int prec) { return prec == HELM_C128 ? sizeof(double2
 // Right-hand sides per wave and the k-split of a launch: with a single right-hand side per problem
 // every row group of a wave works on it (split block-vector products); otherwise one right-hand
 // side per row group.
+// Right-hand sides per sweep wave: a wave has q row groups; with a k-split of ks groups per
+// right-hand side it serves q / ks right-hand sides, each row-dot product split ks ways.  A single
+// right-hand side always takes the full split.  HELM_SWEEP_KSPLIT (1, 2, 4, ...) overrides the
+// choice for chains with several right-hand sides (values that do not divide q are ignored).
+static int ksplit_override() {
+    const char* e = std::getenv("HELM_SWEEP_KSPLIT");
+    return e ? std::atoi(e) : 0;
+}
 static void rhs_grouping(int B, int max_nrhs, int* Q, int* ks, int* Qm, int* ksm) {
     const int q = chain_rhs_per_wave(B), qm = middle_rhs_per_wave(B);
-    *ks = max_nrhs == 1 ? q : 1;
-    *ksm = max_nrhs == 1 ? qm : 1;
+    const int ov = ksplit_override();
+    // measured on the batched uneven workload: two groups per right-hand side beat one and four
+    *ks = max_nrhs == 1 ? q : std::min(2, q);
+    *ksm = max_nrhs == 1 ? qm : std::min(2, qm);
+    if (max_nrhs > 1 && ov >= 1) {
+        if (q % ov == 0) *ks = ov;
+        if (qm % ov == 0) *ksm = ov;
+    }
     *Q = q / *ks;
     *Qm = qm / *ksm;
 }
@@ -397,7 +412,7 @@ static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
     int Q, Qm;
     rhs_grouping(B, nrhs, &Q, &M->ks_chain, &Qm, &M->ks_mid);
     const int groups = (nrhs + Q - 1) / Q, mgroups = (nrhs + Qm - 1) / Qm;
-    const int64_t per = (int64_t)n * 64 * 2;
+    const int64_t per = chain_spill_elems(n);
     const size_t need = compute_elem(M->prec) * (size_t)per * (size_t)std::max(2 * groups, mgroups);
     int rc;
     if (M->spill.bytes < need) {
@@ -463,7 +478,7 @@ extern "C" int sweep_subsolve(sweep_factors_t M, int32_t sub, const void* g, voi
     const int bs = M->sub_rows[sub];
     const int Q = 64 / chain_padded_rows(bs);
     const int groups = (nrhs + Q - 1) / Q;
-    const size_t need = compute_elem(M->prec) * (size_t)M->A->n * 64 * 2 * groups;
+    const size_t need = compute_elem(M->prec) * (size_t)chain_spill_elems(M->A->n) * groups;
     int rc;
     if (M->spill.bytes < need) {
         HIPCHK(hipStreamSynchronize(s));
@@ -566,13 +581,13 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
         for (int g = 0; g * Q < b->nrhs[p]; ++g)
             for (int f = 0; f < 2; ++f) {
                 ch.push_back(ChainDev{p, f, g * Q, std::min(Q, b->nrhs[p] - g * Q), so});
-                so += (int64_t)A[p]->n * 64 * 2;
+                so += chain_spill_elems(A[p]->n);
             }
     int64_t mo = 0;
     for (int p : order)
         for (int g = 0; g * Qm < b->nrhs[p]; ++g) {
             md.push_back(ChainDev{p, 0, g * Qm, std::min(Qm, b->nrhs[p] - g * Qm), mo});
-            mo += (int64_t)A[p]->n * 64 * 2;
+            mo += chain_spill_elems(A[p]->n);
         }
     b->nchains = (int)ch.size();
     b->nmids = (int)md.size();

@@ -64,8 +64,12 @@ bool launch_middle(int B, int prec, int in_prec, int out_prec, int ksplit, const
 // Lanes per row group (right-hand sides per wave) for chains of strip height B and for the middle.
 int chain_rhs_per_wave(int B);
 int middle_rhs_per_wave(int B);
-// Padded rows per right-hand side inside a wave (each chain's workspace is 2 * n * 64 complex).
+// Padded rows per right-hand side inside a wave.
 int chain_padded_rows(int B);
+// Workspace of one chain, in complex elements of the compute precision: the forward products of
+// two strips (2 * n * 64) and a 1 KiB slot per wave that absorbs the stores of ticks without output.
+constexpr int64_t kSpillPad = 128;
+__host__ __device__ inline int64_t chain_spill_elems(int n) { return (int64_t)n * 64 * 2 + kSpillPad; }
 
 // Test hook: full-input / full-output solve of one strip (complex128 vectors [nrhs][rows][n]).
 bool launch_subsolve(int bs, int prec, const ProbDev* prob, const void* fac, const double2* ris2, int rstep, int cdir,

@@ -39,15 +39,6 @@ template <class TF, int BS> struct ColChunks {
     static constexpr int NCH = (N16 + 63) / 64;                      // chunks per lane
 };
 
-// One strip of the program a wave runs.
-struct StripRT {
-    const char* fac;    // first stored column
-    int d;              // column direction
-    int jl;             // layer row
-    int full;           // every row in / out (front blocks F, E and the test hook)
-    int kind, j0, rdir; // profile kind, physical row of local row 0, row direction
-};
-
 __device__ __forceinline__ double2 ld2(const HS_GLOBAL double2* p) { return gld(p); }
 __device__ __forceinline__ double2 ld2(const HS_GLOBAL float2* p) { const float2 v = gld(p); return make_double2(v.x, v.y); }
 template <class TO, class T> __device__ __forceinline__ TO cvt_out(C2<T> v);
@@ -63,6 +54,26 @@ struct SubArg {
     const double2* ris2;    // 1/s2 of local row r at ris2[rstep * r]
     int nrhs, rstep, cdir, jl;
 };
+
+// Sum of v over lanes l and l ^ OFF (OFF = 16 or 32), in every lane, with the gfx950 row / half-wave
+// swap instructions (no LDS round trip).
+template <int OFF> __device__ __forceinline__ float xor_sum(float v) {
+    const unsigned b = __float_as_uint(v);
+    const auto s = OFF == 16 ? __builtin_amdgcn_permlane16_swap(b, b, false, false)
+                             : __builtin_amdgcn_permlane32_swap(b, b, false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+template <int OFF> __device__ __forceinline__ double xor_sum(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    const auto sl = OFF == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                              : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto sh = OFF == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                              : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const double a = __longlong_as_double((long long)(((uint64_t)sh[0] << 32) | sl[0]));
+    const double c = __longlong_as_double((long long)(((uint64_t)sh[1] << 32) | sl[1]));
+    return a + c;
+}
 
 template <class T, class TF, class TI, class TO, int BS, int MODE, int D, int KS>
 __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
@@ -108,7 +119,9 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
     const int rr = rok ? r : 0;
     const HS_GLOBAL TI* __restrict__ fin = gptr((const TI*)IO.in + rhs * N);
     HS_GLOBAL TO* __restrict__ y = gptr((TO*)IO.out + rhs * N);
-    HS_GLOBAL C2<T>* __restrict__ spill = gptr(spill_base + (MODE == MODE_SUB ? (int64_t)blockIdx.x * 2 * n * 64 : ch.spill_off));
+    HS_GLOBAL C2<T>* __restrict__ spill = gptr(spill_base + (MODE == MODE_SUB ? (int64_t)blockIdx.x * chain_spill_elems(n) : ch.spill_off));
+    // per-lane 16-byte slot after the workspace: the target of stores of ticks that have no output
+    HS_GLOBAL char* const dummy = (HS_GLOBAL char*)(spill + (int64_t)2 * n * 64) + 16 * lane;
     const HS_GLOBAL char* const facbase = gptr(MODE == MODE_SUB ? (const char*)sa.fac : (const char*)IO.fac);
     const HS_GLOBAL double2* const sag = gptr(sa.g);
     HS_GLOBAL double2* const sax = gptr(sa.x);
@@ -165,48 +178,51 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
         return is2_other;
     };
 
+    static_assert(D % 2 == 0, "the staging parity k & 1 must be a compile-time value");
     // register ring
     chunk16 rbk[D][NCH], rfk[D][NCH];
     CT rsp[D];
     double2 ra[D], rb2[D], rc[D];
 
-    const int T1 = n + 1;
-    const int nticks = (m + 2) * T1;
+    // A pair (strip i-1 backward, strip i forward) takes n + 1 ticks, padded to whole groups of D.
+    const int TP = (n + 1 + D - 1) / D * D;
+    const int G = TP / D;
+    const int64_t colbytes = (int64_t)sizeof(CF) * STRIDE;
 
-    // Prefetch cursor (pair pi, tick pk), D ticks ahead of execution.  Loads are unconditional:
-    // positions past the end are clamped to valid memory and their values are never used, so each
-    // tick issues the same load sequence and the compiler waits on exactly the loads issued D ticks
-    // earlier.  Strip-dependent bases are recomputed only when the cursor enters a new pair.
-    int pi = 0, pk = 0, pdir = 1;
-    const HS_GLOBAL char* pfb = facbase;         // backward strip pi-1
-    const HS_GLOBAL char* pff = facbase;         // forward strip pi
-    const HS_GLOBAL C2<T>* pspb = spill;         // workspace of strip pi-1
+    // Prefetch cursor: group pg of pair pi, one group (D ticks) ahead of execution.  Loads are
+    // unconditional: positions past the end are clamped to valid memory and their values are never
+    // used.  Strip-dependent bases are recomputed only when the cursor enters a new pair.
+    int pi = 0, pg = 0, pdir = 1;
+    const HS_GLOBAL char* pfb = facbase;         // backward strip pi-1, column n-1 (stepping down)
+    const HS_GLOBAL char* pff = facbase;         // forward strip pi, column 0 (stepping up)
+    const HS_GLOBAL C2<T>* pspb = spill;         // workspace of strip pi-1, step n-1
     const HS_GLOBAL TI* pfrow = fin;             // MODE_FWD: input row of strip pi
     const HS_GLOBAL TO* pyrow = y;               // MODE_BWD: output row of strip pi-1
     auto pset = [&]() __attribute__((always_inline)) {
         const int pc = pi <= m + 1 ? pi : m + 1;
         const int ib = pc >= 1 ? pc - 1 : 0, ifw = pc <= m ? pc : m;
         pdir = strip_dir(pc);
-        pfb = strip_fac(ib);
+        pfb = strip_fac(ib) + colbytes * (n - 1);
         pff = strip_fac(ifw);
-        pspb = spill + (int64_t)(ib & 1) * n * 64 + lane;
+        pspb = spill + (int64_t)(ib & 1) * n * 64 + (int64_t)(n - 1) * 64 + lane;
         if (MODE == MODE_FWD) pfrow = fin + (int64_t)(strip_row(ifw, strip_full(ifw)) - 1) * n;
         if (MODE == MODE_BWD) pyrow = y + (int64_t)(strip_row(ib, strip_full(ib)) - 1) * n;
     };
     pset();
-    auto prefetch = [&](chunk16 (&bk)[NCH], chunk16 (&fk)[NCH], CT& sp, double2& a0, double2& a1,
+    auto prefetch = [&](int u, chunk16 (&bk)[NCH], chunk16 (&fk)[NCH], CT& sp, double2& a0, double2& a1,
                         double2& a2) __attribute__((always_inline)) {
+        const int pk = pg * D + u;
         const int k2 = pk < n ? pk : n - 1;
         const int col = pdir > 0 ? k2 + 1 : n - k2;
-        const HS_GLOBAL chunk16* srcb = (const HS_GLOBAL chunk16*)(pfb + (int64_t)(sizeof(CF) * STRIDE) * (n - 1 - k2));
-        const HS_GLOBAL chunk16* srcf = (const HS_GLOBAL chunk16*)(pff + (int64_t)(sizeof(CF) * STRIDE) * k2);
+        const HS_GLOBAL chunk16* srcb = (const HS_GLOBAL chunk16*)(pfb - colbytes * k2);
+        const HS_GLOBAL chunk16* srcf = (const HS_GLOBAL chunk16*)(pff + colbytes * k2);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
             bk[c] = srcb[idx];
             fk[c] = srcf[idx];
         }
-        sp = gld(pspb + (int64_t)(n - 1 - k2) * 64);
+        sp = gld(pspb - (int64_t)k2 * 64);
         if (MODE == MODE_FWD) {
             a0 = ld2(pfrow + col - 1);
         } else if (MODE == MODE_BWD) {
@@ -219,7 +235,9 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
         } else {
             a0 = gld(sag + ((int64_t)rhs * BS + rr) * n + col - 1);
         }
-        if (++pk == T1) { pk = 0; ++pi; pset(); }
+    };
+    auto prefetch_next_group = [&]() __attribute__((always_inline)) {
+        if (++pg == G) { pg = 0; ++pi; pset(); }
     };
 
     // Lambda^{-1} row r of a staged column (packed upper triangle) times the exchange vector of group q:
@@ -243,11 +261,10 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
             else acc0 = cfma<T>(l, t, acc0);
         }
         CT acc = cadd<T>(acc0, acc1);
-#pragma unroll
-        for (int off = RP; off < RP * KS; off <<= 1) {
-            acc.x += __shfl_xor(acc.x, off);
-            acc.y += __shfl_xor(acc.y, off);
-        }
+        // sum of the KS partial products over the row groups of one right-hand side (lanes r + RP j):
+        // a butterfly over the lane offsets RP, 2 RP, ..., RP * KS / 2
+        if (RP <= 16 && RP * KS >= 32) { acc.x = xor_sum<16>(acc.x); acc.y = xor_sum<16>(acc.y); }
+        if (RP <= 32 && RP * KS >= 64) { acc.x = xor_sum<32>(acc.x); acc.y = xor_sum<32>(acc.y); }
         return acc;
     };
     auto colscalar = [&](const chunk16* colv, int which) __attribute__((always_inline)) -> CT {
@@ -256,37 +273,50 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
 
     static_for<D>([&](auto UC) __attribute__((always_inline)) {
         constexpr int u = decltype(UC)::value;
-        prefetch(rbk[u], rfk[u], rsp[u], ra[u], rb2[u], rc[u]);
+        prefetch(u, rbk[u], rfk[u], rsp[u], ra[u], rb2[u], rc[u]);
     });
+    prefetch_next_group();
 
-    bool full_b = false, full_f = false;
-    int row_b = 1, row_f = 1;
-    CT is2b = mk<T>(0, 0), is2f = mk<T>(0, 0);
     CT xcur = mk<T>(0, 0), z = mk<T>(0, 0), w = mk<T>(0, 0), wcarry = mk<T>(0, 0), ypart = mk<T>(0, 0);
     CT wlag[LAG], wsnap[LAG];
 #pragma unroll
     for (int j = 0; j < LAG; ++j) { wlag[j] = mk<T>(0, 0); wsnap[j] = mk<T>(0, 0); }
 
-    int i = 0, k = 0;                                   // execution cursor: pair i, tick k
-    for (int K0 = 0; K0 < nticks; K0 += D) {
-        static_for<D>([&](auto UC) __attribute__((always_inline)) {
-            constexpr int u = decltype(UC)::value;
-            const int K = K0 + u;
-            if (K < nticks) {
-                if (k == 0) {
-                    const int ib = i >= 1 ? i - 1 : 0, ifw = i <= m ? i : m;
-                    full_b = strip_full(ib); row_b = strip_row(ib, full_b); is2b = strip_is2(ib);
-                    full_f = strip_full(ifw); row_f = strip_row(ifw, full_f); is2f = strip_is2(ifw);
-                }
-                const bool bon = i >= 1 && k < n;
-                const bool fon = i <= m && k >= 1;
-                const bool fin_on = i <= m && k < n;
-                const int col = colof(strip_dir(i), k);
+    // Every tick issues the same sequence of global loads and stores (stores without output go to
+    // the dummy slot), so the compiler's memory waits at each tick cover exactly the loads issued
+    // D ticks earlier.
+    for (int i = 0; i <= m + 1; ++i) {
+        // pair i: backward pass of strip i-1 (i >= 1), forward pass of strip i (i <= m)
+        const int ib = i >= 1 ? i - 1 : 0, ifw = i <= m ? i : m;
+        const bool full_b = strip_full(ib), full_f = strip_full(ifw);
+        const int row_b = strip_row(ib, full_b);
+        const CT is2b = strip_is2(ib), is2f = strip_is2(ifw);
+        const int cd = strip_dir(i);
+        const bool pb = i >= 1, pf = i <= m;
+        // layer output of this pair's backward pass: row base and whether this lane writes it
+        bool wy;
+        HS_GLOBAL TO* yrow;
+        if (MODE == MODE_FWD || MODE == MODE_BWD) { wy = full_b ? own : oslot; yrow = y + (int64_t)(row_b - 1) * n; }
+        else if (MODE == MODE_MID) { wy = oslot; yrow = y + (int64_t)(cmid - 1) * n; }
+        else { wy = own; yrow = (HS_GLOBAL TO*)sax + ((int64_t)rhs * BS + r) * n; }
+        wy = wy && pb;
+        HS_GLOBAL CT* const spw = spill + (int64_t)(i & 1) * n * 64 + lane;   // forward products of strip i
+
+        for (int kb = 0; kb < G; ++kb) {
+            static_for<D>([&](auto UC) __attribute__((always_inline)) {
+                constexpr int u = decltype(UC)::value;
+                const int k = kb * D + u;
+                const bool bon = k < n;                 // with pb: step n-1-k of strip i-1
+                const bool fon = pf && k >= 1 && k <= n;
+                const bool fin_on = pf && k < n;
+                const int col = cd > 0 ? k + 1 : n - k;
                 // stage the columns of this tick and the exchange vectors
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
-                    const int idx = c * 64 + lane;
-                    if (idx < N16) { colb[idx] = rbk[u][c]; colf[k & 1][idx] = rfk[u][c]; }
+                    // lanes past the column hold the clamped last chunk and rewrite it unchanged
+                    const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
+                    colb[idx] = rbk[u][c];
+                    colf[u & 1][idx] = rfk[u][c];
                 }
                 xbx[q][r] = cmul<T>(is2b, xcur);
                 xfx[q][r] = z;
@@ -297,30 +327,23 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
                 for (int j = 0; j < LAG; ++j) ws = (k == j + 1) ? wsnap[j] : ws;
                 const CT xb = cfms<T>(colscalar(colb, XCOL_E), rowdot(colb, xbx), ws);
                 // forward pass of strip i: product for step k-1
-                const chunk16* cprev = colf[(k + 1) & 1];
+                const chunk16* cprev = colf[(u + 1) & 1];
                 const CT wf = rowdot(cprev, xfx);
-                if (bon) {
-                    const CT x = k == 0 ? wcarry : xb;
+                // layer output of the backward pass
+                const CT x = k == 0 ? wcarry : xb;
+                const CT yval = MODE == MODE_BWD ? csub<T>(ccast<T, double>(rb2[u]), x) : x;
+                gst((wy && bon) ? yrow + col - 1 : (HS_GLOBAL TO*)dummy, cvt_out<TO, T>(yval));
+                if (pb && bon) {
                     xcur = x;
-                    if (MODE == MODE_FWD) {
-                        if (full_b ? own : oslot) gst(y + (int64_t)(row_b - 1) * n + col - 1, cvt_out<TO, T>(x));
-                        ypart = x;
-                    } else if (MODE == MODE_BWD) {
-                        const CT yn = csub<T>(ccast<T, double>(rb2[u]), x);
-                        if (full_b ? own : oslot) gst(y + (int64_t)(row_b - 1) * n + col - 1, cvt_out<TO, T>(yn));
-                        ypart = yn;
-                    } else if (MODE == MODE_MID) {
-                        if (oslot) gst(y + (int64_t)(cmid - 1) * n + col - 1, cvt_out<TO, T>(x));
-                    } else {
-                        if (own) gst(sax + ((int64_t)rhs * BS + r) * n + col - 1, cvt_out<double2, T>(x));
-                    }
+                    ypart = yval;
                 }
+                // forward product of step k-1 into the workspace
+                gst(fon ? spw + (int64_t)(k - 1) * 64 : (HS_GLOBAL CT*)dummy, wf);
                 if (fon) {
 #pragma unroll
                     for (int j = LAG - 1; j >= 1; --j) wlag[j] = wlag[j - 1];
                     wlag[0] = w;
                     w = wf;
-                    gst(spill + (int64_t)(i & 1) * n * 64 + (int64_t)(k - 1) * 64 + lane, w);
                     if (k == n) {
                         wcarry = w;
 #pragma unroll
@@ -328,7 +351,7 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
                     }
                 }
                 if (fin_on) {
-                    const chunk16* cc = colf[k & 1];
+                    const chunk16* cc = colf[u & 1];
                     CT g = mk<T>(0, 0);
                     if (MODE == MODE_FWD) {
                         double2 gv = ra[u];
@@ -346,10 +369,10 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
                     }
                     z = k == 0 ? g : cfms<T>(cmul<T>(colscalar(cprev, XCOL_E), is2f), w, g);
                 }
-                prefetch(rbk[u], rfk[u], rsp[u], ra[u], rb2[u], rc[u]);
-                if (++k == T1) { k = 0; ++i; }
-            }
-        });
+                prefetch(u, rbk[u], rfk[u], rsp[u], ra[u], rb2[u], rc[u]);
+            });
+            prefetch_next_group();
+        }
     }
 }
 
@@ -359,21 +382,37 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
 // prefetch distance in ticks: as deep as the register budget of one wave allows
 template <class T, int BS> struct Ring { static constexpr int D = (sizeof(T) == 8 || BS > 17) ? 2 : 4; };
 
+template <class T, class TF, class TI, class TO, int BV, int MODE>
+static bool sweep_bs(int ks, const ProbDev* probs, const ChainDev* chains, int nblocks, const IoDev* io, IoDev iov,
+                     C2<T>* sp, const SubArg& sa, hipStream_t s) {
+    constexpr int Q = RowsOf<BV>::Q, DV = Ring<T, BV>::D;
+    dim3 g(nblocks), b(64);
+    if (ks == 1) {
+        hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, DV, 1>), g, b, 0, s, probs, chains, io, iov, sp, sa);
+        return true;
+    }
+    if constexpr (Q >= 4) {
+        if (ks == 2) {
+            hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, DV, 2>), g, b, 0, s, probs, chains, io, iov, sp, sa);
+            return true;
+        }
+    }
+    if constexpr (Q >= 2) {
+        if (ks == Q) {
+            hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, DV, Q>), g, b, 0, s, probs, chains, io, iov, sp, sa);
+            return true;
+        }
+    }
+    return false;
+}
+
 template <class T, class TF, class TI, class TO, int MODE>
 static bool sweep_typed(int bs, int ks, const ProbDev* probs, const ChainDev* chains, int nblocks, const IoDev* io,
                         IoDev iov, void* spill, const SubArg& sa, hipStream_t s) {
-    dim3 g(nblocks), b(64);
     C2<T>* sp = (C2<T>*)spill;
     switch (bs) {
-#define HS_CASE(BV)                                                                                               \
-    case BV:                                                                                                      \
-        if (ks == 1)                                                                                              \
-            hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, Ring<T, BV>::D, 1>), g, b, 0, s, probs, chains, io, \
-                               iov, sp, sa);                                                                      \
-        else                                                                                                      \
-            hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, Ring<T, BV>::D, RowsOf<BV>::Q>), g, b, 0, s, probs,  \
-                               chains, io, iov, sp, sa);                                                          \
-        return true;
+#define HS_CASE(BV) \
+    case BV: return sweep_bs<T, TF, TI, TO, BV, MODE>(ks, probs, chains, nblocks, io, iov, sp, sa, s);
         HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13) HS_CASE(17) HS_CASE(25) HS_CASE(33)
 #undef HS_CASE
         default: return false;
@@ -388,6 +427,8 @@ static bool sweep_prec(int bs, int ks, int prec, int in_prec, int out_prec, cons
             return sweep_typed<double, double, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, sa, s);
         return false;
     }
+    if (in_prec == 0 && out_prec == 0)
+        return sweep_typed<float, float, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, sa, s);
     if (in_prec == 0 && out_prec == 1)
         return sweep_typed<float, float, double2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, sa, s);
     if (in_prec == 1 && out_prec == 1)

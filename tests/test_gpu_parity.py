@@ -292,3 +292,45 @@ def test_batch_refactor_equals_individual(hs, torch, prec):
     for F, f, u0 in zip(facs, fs, ref):
         u = F.apply(f).cpu().numpy()
         assert np.array_equal(u, u0)
+
+
+@pytest.mark.parametrize("ks", [1, 2, 4])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sweep_ksplit_parity(hs, torch, monkeypatch, ks, prec):
+    """Every right-hand-side grouping of the sweep waves (row-dot products split 1, 2 or 4 ways)
+    gives the oracle's M f, for a single problem and for an uneven batch."""
+    monkeypatch.setenv("HELM_SWEEP_KSPLIT", str(ks))
+    _log("ksplit", ks, "prec", prec)
+    op, c = _case("cfg1")
+    A = _gpu_problem(hs, torch, op, c)
+    F = hs.Factors(A, prec)
+    Mo = OS.factor(op, c)
+    f = workloads.random_rhs(op.n, 5, seed=40 + ks)
+    fd = torch.as_tensor(f, device="cuda")
+    if prec == hs.HELM_C64:
+        u = F.apply(fd.to(torch.complex64)).cpu().numpy().astype(np.complex128)
+        uo = OS.apply_sweep(Mo, f.astype(np.complex64).astype(np.complex128))
+        tol = 1e-4
+    else:
+        u = F.apply(fd).cpu().numpy()
+        uo = OS.apply_sweep(Mo, f)
+        tol = 1e-10
+    err = _rel(u, uo)
+    _log(f"  single rel {err:.2e}")
+    assert err <= tol
+    # batch: this problem with 5 right-hand sides next to a smaller one with 3
+    op2, c2 = _case("grf45")
+    op2 = OH.Params(n=op2.n, omega=op2.omega, alpha=2.0, pml_w=8, mpml_w=8)
+    A2 = _gpu_problem(hs, torch, op2, c2)
+    F2 = hs.Factors(A2, prec)
+    f2 = workloads.random_rhs(op2.n, 3, seed=50 + ks)
+    b = hs.Batch([A, A2], [F, F2], [5, 3], restart=5)
+    ub = b.apply([fd, torch.as_tensor(f2, device="cuda")])
+    Mo2 = OS.factor(op2, c2)
+    uo2 = OS.apply_sweep(Mo2, f2)
+    # the batched apply takes complex128 vectors; with complex64 factors its error is the factors'
+    btol = 1e-10 if prec == 0 else 1e-4
+    e1 = _rel(ub[0].cpu().numpy(), OS.apply_sweep(Mo, f))
+    e2 = _rel(ub[1].cpu().numpy(), uo2)
+    _log(f"  batch rel {e1:.2e} {e2:.2e}")
+    assert e1 <= btol and e2 <= btol
