@@ -391,6 +391,18 @@ static int ksplit_override() {
     const char* e = std::getenv("HELM_SWEEP_KSPLIT");
     return e ? std::atoi(e) : 0;
 }
+// Waves per sweep chain: 2 (backward and forward pass on separate waves) unless HELM_SWEEP_WAVES=1.
+static bool two_wave_chains(int B) {
+    const char* e = std::getenv("HELM_SWEEP_WAVES");
+    return B <= 17 && !(e && std::atoi(e) == 1);
+}
+static bool run_chains(int B, int prec, int in_prec, int out_prec, int phase, int ks, const ProbDev* probs,
+                       const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
+    if (two_wave_chains(B))
+        return launch_chains2(B, prec, in_prec, out_prec, phase, ks, probs, chains, nchains, io, io_val, spill, s);
+    return launch_chains(B, prec, in_prec, out_prec, phase, ks, probs, chains, nchains, io, io_val, spill, s);
+}
+
 static void rhs_grouping(int B, int max_nrhs, int* Q, int* ks, int* Qm, int* ksm) {
     const int q = chain_rhs_per_wave(B), qm = middle_rhs_per_wave(B);
     const int ov = ksplit_override();
@@ -450,7 +462,7 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
     const int B = M->A->B;
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
-        if (!launch_chains(B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
+        if (!run_chains(B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
                            nullptr, io, M->spill.p, s))
             return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
         LAUNCHCHK();
@@ -463,7 +475,7 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
     }
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
-        launch_chains(B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains, nullptr,
+        run_chains(B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains, nullptr,
                       io, M->spill.p, s);
         LAUNCHCHK();
     }
@@ -717,7 +729,7 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, hipStream_
     const IoDev none{nullptr, nullptr, nullptr};
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
-        if (!launch_chains(b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
+        if (!run_chains(b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
                            b->spill.p, s))
             return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
         LAUNCHCHK();
@@ -729,7 +741,7 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, hipStream_
     }
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
-        launch_chains(b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
+        run_chains(b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
                       b->spill.p, s);
         LAUNCHCHK();
     }

@@ -59,6 +59,10 @@ bool launch_factor(int bs, int prec, const ProbDev* probs, const SubDev* subs, i
 // groups per wave (all groups serve one right-hand side, splitting each block-vector product).
 bool launch_chains(int B, int prec, int in_prec, int out_prec, int phase, int ksplit, const ProbDev* probs,
                    const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s);
+// The same chains with two waves per chain (backward and forward pass on separate waves, one LDS
+// barrier per step); strip heights up to 17.
+bool launch_chains2(int B, int prec, int in_prec, int out_prec, int phase, int ksplit, const ProbDev* probs,
+                    const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s);
 bool launch_middle(int B, int prec, int in_prec, int out_prec, int ksplit, const ProbDev* probs,
                    const ChainDev* mids, int nmids, const IoDev* io, IoDev io_val, void* spill, hipStream_t s);
 // Lanes per row group (right-hand sides per wave) for chains of strip height B and for the middle.

@@ -1,0 +1,347 @@
+// a3 / a4 with two waves per chain: the backward pass of strip i-1 and the forward pass of strip i
+// (Algorithm 4, one front) run on different waves of one workgroup instead of interleaved in one.
+//
+// The chain's schedule is the one of the single-wave kernel: pair i = (backward pass of strip i-1,
+// forward pass of strip i), n + 1 ticks per pair, consecutive strips in opposite column directions so
+// that the backward pass of strip i-1 emits its layer row in the column order in which the forward
+// pass of strip i consumes it.  Here wave B runs tick k of pair i at step (i, k) and wave F runs the
+// same tick one step later, at (i, k + 1); pairs are padded to at least n + 2 steps so that F's last
+// slot of a pair is always idle.  Per step:
+//   B: x_k = w_{n-1-k} - Lambda^{-1} (e x_{k-1}) (backward step), stores the layer output, and hands
+//      it to F through LDS (slot k & 1);
+//   F: w = Lambda^{-1} z (forward step), stores it to the workspace, then z = g - e w with g built
+//      from the input and B's layer output of the previous step;
+//   one LDS barrier (no wait on global memory).
+// Forward products go to a global workspace; B reads those of strip i-1 during pair i.  Those of the
+// last D steps are also handed over in LDS: every workspace value B prefetches was stored by F at
+// least D steps before, so F's own wait for its ring loads of that step (issued after the store)
+// completes the store before a barrier that precedes B's load.
+#include "hs_sweep_util.h"
+
+namespace hs {
+
+// Workgroup-wide LDS ordering for one step: this wave's LDS writes complete (lgkmcnt(0)), then the
+// barrier.  Outstanding global loads and stores are not waited for.
+__device__ __forceinline__ void step_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // vmcnt 63, expcnt 7, lgkmcnt 0
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T, class TF, class TI, class TO, int BS, int MODE, int D, int KS>
+__global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
+                                               const IoDev* __restrict__ io, IoDev io_val, C2<T>* __restrict__ spill_base) {
+    static_assert(MODE == MODE_FWD || MODE == MODE_BWD, "two-wave chains serve the front phases");
+    static_assert(D % 2 == 0, "slot parities must be compile-time values");
+    using CT = C2<T>;
+    using CF = C2<TF>;
+    constexpr int RP = RowsOf<BS>::RP, Q = RowsOf<BS>::Q;
+    using CC = ColChunks<TF, BS>;
+    constexpr int STRIDE = CC::STRIDE, N16 = CC::N16, NCH = CC::NCH;
+    constexpr int PACK = packed_size(BS);
+    __shared__ chunk16 colb[N16];        // B: column of this step
+    __shared__ chunk16 colf[2][N16];     // F: columns of this and the previous step
+    __shared__ CT xbx[Q][RP];            // B: exchange vector
+    __shared__ CT xfx[Q][RP];            // F: exchange vector
+    __shared__ CT xlay[2][64];           // B -> F: layer output, by step parity
+    __shared__ CT whand[D][64];          // F -> B: forward products of the last D steps of a strip
+
+    const int role = threadIdx.x >> 6;   // 0: backward pass (B), 1: forward pass (F); wave-uniform
+    const int lane = threadIdx.x & 63, r = lane % RP, q = lane / RP;
+    const int rq = q / KS, kg = q % KS;
+    constexpr int KMAX = (BS + KS - 1) / KS;
+    const ChainDev ch = chains[blockIdx.x];
+    const ProbDev& P = probs[ch.prob];
+    const IoDev IO = io ? io[ch.prob] : io_val;
+    const int n = P.n, B = P.B, cmid = P.c;
+    const int L = ch.front == 0 ? P.L_lo : P.L_up;
+    const int sub0 = ch.front == 0 ? 0 : P.L_lo + 1;
+    const int64_t N = (int64_t)n * n;
+    const int nq = ch.nq;
+    const bool qok = rq < nq;
+    const bool rok = r < BS;
+    const bool act = qok && rok;
+    const bool own = act && kg == 0;
+    const bool slot = act && r == B - 1;
+    const bool oslot = slot && kg == 0;
+    const int rhs = ch.rhs0 + (qok ? rq : 0);
+    const int rr = rok ? r : 0;
+    const HS_GLOBAL TI* __restrict__ fin = gptr((const TI*)IO.in + rhs * N);
+    HS_GLOBAL TO* __restrict__ y = gptr((TO*)IO.out + rhs * N);
+    HS_GLOBAL CT* __restrict__ spill = gptr(spill_base + ch.spill_off);
+    HS_GLOBAL char* const dummy = (HS_GLOBAL char*)(spill + (int64_t)2 * n * 64) + 16 * lane;
+    const HS_GLOBAL char* const facbase = gptr((const char*)IO.fac);
+
+    // the program: strips 0..m in processing order
+    const int dirF = ch.front == 0 ? 1 : -1;
+    const int jF = ch.front == 0 ? B : n + 1 - B;
+    const int64_t bstride = (int64_t)n * col_stride<TF>(B);
+    const int m = L;
+    auto strip_t = [&](int i) __attribute__((always_inline)) { return MODE == MODE_FWD ? i : L - i; };
+    auto strip_dir = [&](int i) __attribute__((always_inline)) -> int { return (strip_t(i) & 1) ? -1 : 1; };
+    auto strip_fac = [&](int i) __attribute__((always_inline)) -> const HS_GLOBAL char* {
+        return facbase + sizeof(CF) * ((int64_t)(sub0 + strip_t(i)) * bstride);
+    };
+    auto strip_full = [&](int i) __attribute__((always_inline)) -> bool { return strip_t(i) == 0; };
+    auto strip_row = [&](int i, bool full) __attribute__((always_inline)) -> int {
+        const int jl = jF + dirF * strip_t(i);
+        return full ? jl - dirF * (B - 1 - rr) : jl;
+    };
+    CT is2_front, is2_other;
+    {
+        double2 s2, is2, lo, hi;
+        strip_profile(P, SUB_PHYS, jF - dirF * (B - 1), dirF, rr, s2, is2, lo, hi);
+        is2_front = ccast<T, double>(is2);
+        strip_profile(P, SUB_MOVE, 0, 1, rr, s2, is2, lo, hi);
+        is2_other = ccast<T, double>(is2);
+    }
+    auto strip_is2 = [&](int i) __attribute__((always_inline)) -> CT { return strip_t(i) == 0 ? is2_front : is2_other; };
+
+    // A pair takes n + 1 ticks for B and the same ticks one step later for F: at least n + 2 steps,
+    // padded to whole groups of D.
+    const int TP = (n + 2 + D - 1) / D * D;
+    const int G = TP / D;
+    const int64_t colbytes = (int64_t)sizeof(CF) * STRIDE;
+
+    int loff[KMAX];
+#pragma unroll
+    for (int jj = 0; jj < KMAX; ++jj) {
+        const int k = kg + KS * jj < BS ? kg + KS * jj : BS - 1;
+        loff[jj] = (k >= rr) ? (rr * BS - (rr * (rr - 1)) / 2 + (k - rr)) : (k * BS - (k * (k - 1)) / 2 + (rr - k));
+    }
+    auto rowdot = [&](const chunk16* colv, const CT (*xv)[RP]) __attribute__((always_inline)) -> CT {
+        const CF* cf = (const CF*)colv;
+        CT acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
+#pragma unroll
+        for (int jj = 0; jj < KMAX; ++jj) {
+            const int k = kg + KS * jj;
+            const CT l = ccast<T, TF>(cf[loff[jj]]);
+            const CT xk = xv[q][KS == 1 ? jj : (k < BS ? k : 0)];
+            const CT t = (KS == 1 || k < BS) ? xk : mk<T>(0, 0);
+            if (jj & 1) acc1 = cfma<T>(l, t, acc1);
+            else acc0 = cfma<T>(l, t, acc0);
+        }
+        CT acc = cadd<T>(acc0, acc1);
+        if (RP <= 16 && RP * KS >= 32) { acc.x = xor_sum<16>(acc.x); acc.y = xor_sum<16>(acc.y); }
+        if (RP <= 32 && RP * KS >= 64) { acc.x = xor_sum<32>(acc.x); acc.y = xor_sum<32>(acc.y); }
+        return acc;
+    };
+    auto colscalar = [&](const chunk16* colv, int which) __attribute__((always_inline)) -> CT {
+        return ccast<T, TF>(((const CF*)colv)[PACK + which]);
+    };
+
+    // Each role runs its own loop nest (its own prefetch sequence, so the compiler's waits cover
+    // exactly the loads of one group earlier); both execute one barrier per step.
+    auto run = [&](auto RC) __attribute__((always_inline)) {
+        constexpr int ROLE = decltype(RC)::value;
+        // register ring: the column of this wave's strip; B: workspace value and (backward phase)
+        // its own output row of the forward phase; F: the input row
+        chunk16 rk[D][NCH];
+        CT rsp[D];
+        double2 ra[D];
+
+        // Prefetch cursor (step pk of pair pi), one group ahead.  B at step pk needs tick pk of pair
+        // pi, F tick pk - 1.  Positions outside a strip are clamped to valid memory (values unused).
+        int pi = 0, pg = 0, pdir = 1;
+        const HS_GLOBAL char* pcol = facbase;   // B: column n-1 of strip pi-1; F: column 0 of strip pi
+        const HS_GLOBAL CT* psp = spill;        // B: workspace of strip pi-1 at step n-1
+        const HS_GLOBAL TI* pfrow = fin;        // F, forward phase: input row of strip pi
+        const HS_GLOBAL TO* pyrow = y;          // B, backward phase: output row of strip pi-1
+        auto pset = [&]() __attribute__((always_inline)) {
+            const int pc = pi <= m + 1 ? pi : m + 1;
+            const int ib = pc >= 1 ? pc - 1 : 0, ifw = pc <= m ? pc : m;
+            pdir = strip_dir(pc);
+            if constexpr (ROLE == 0) {
+                pcol = strip_fac(ib) + colbytes * (n - 1);
+                psp = spill + (int64_t)(ib & 1) * n * 64 + (int64_t)(n - 1) * 64 + lane;
+                if (MODE == MODE_BWD) pyrow = y + (int64_t)(strip_row(ib, strip_full(ib)) - 1) * n;
+            } else {
+                pcol = strip_fac(ifw);
+                if (MODE == MODE_FWD) pfrow = fin + (int64_t)(strip_row(ifw, strip_full(ifw)) - 1) * n;
+            }
+        };
+        pset();
+        auto prefetch = [&](int u) __attribute__((always_inline)) {
+            const int pk = pg * D + u;
+            if constexpr (ROLE == 0) {
+                const int k2 = pk < n ? pk : n - 1;
+                const int col = pdir > 0 ? k2 + 1 : n - k2;
+                const HS_GLOBAL chunk16* src = (const HS_GLOBAL chunk16*)(pcol - colbytes * k2);
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) rk[u][c] = src[c * 64 + lane < N16 ? c * 64 + lane : N16 - 1];
+                rsp[u] = gld(psp - (int64_t)k2 * 64);
+                if (MODE == MODE_BWD) ra[u] = ld2(pyrow + col - 1);
+            } else {
+                const int kf = pk - 1;
+                const int k2 = kf < 0 ? 0 : (kf < n ? kf : n - 1);
+                const int col = pdir > 0 ? k2 + 1 : n - k2;
+                const HS_GLOBAL chunk16* src = (const HS_GLOBAL chunk16*)(pcol + colbytes * k2);
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) rk[u][c] = src[c * 64 + lane < N16 ? c * 64 + lane : N16 - 1];
+                if (MODE == MODE_FWD) ra[u] = ld2(pfrow + col - 1);
+                else ra[u] = ld2(y + (int64_t)(cmid - 1) * n + col - 1);
+            }
+        };
+        auto prefetch_next_group = [&]() __attribute__((always_inline)) {
+            if (++pg == G) { pg = 0; ++pi; pset(); }
+        };
+        static_for<D>([&](auto UC) __attribute__((always_inline)) { prefetch(decltype(UC)::value); });
+        prefetch_next_group();
+
+        // B: previous layer-row value; F: z, last forward product, the last D products
+        CT xcur = mk<T>(0, 0), z = mk<T>(0, 0), w = mk<T>(0, 0);
+        CT wlag[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) wlag[j] = mk<T>(0, 0);
+
+        for (int i = 0; i <= m + 1; ++i) {
+            const bool pb = i >= 1, pf = i <= m;
+            const int ib = i >= 1 ? i - 1 : 0, ifw = i <= m ? i : m;
+            const int cd = strip_dir(i);
+            const bool full_b = strip_full(ib);
+            const CT is2b = strip_is2(ib);
+            HS_GLOBAL TO* const yrow = y + (int64_t)(strip_row(ib, full_b) - 1) * n;
+            const bool wy = pb && (full_b ? own : oslot);
+            const bool full_f = strip_full(ifw);
+            const CT is2f = strip_is2(ifw);
+            HS_GLOBAL CT* const spw = spill + (int64_t)(i & 1) * n * 64 + lane;
+
+            for (int kb = 0; kb < G; ++kb) {
+                static_for<D>([&](auto UC) __attribute__((always_inline)) {
+                    constexpr int u = decltype(UC)::value;
+                    const int k = kb * D + u;
+                    if constexpr (ROLE == 0) {
+                        // ---- B: tick k of the backward pass of strip i-1 (step s = n-1-k) ----
+                        const bool bon = pb && k < n;
+                        const int col = cd > 0 ? k + 1 : n - k;
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
+                            colb[idx] = rk[u][c];
+                        }
+                        xbx[q][r] = cmul<T>(is2b, xcur);
+                        wave_sync();
+                        const CT ws = kb == 0 ? whand[u][lane] : rsp[u];   // first group: handed over in LDS
+                        const CT xb = cfms<T>(colscalar(colb, XCOL_E), rowdot(colb, xbx), ws);
+                        const CT x = k == 0 ? ws : xb;
+                        const CT yval = MODE == MODE_BWD ? csub<T>(ccast<T, double>(ra[u]), x) : x;
+                        gst((wy && bon) ? yrow + col - 1 : (HS_GLOBAL TO*)dummy, cvt_out<TO, T>(yval));
+                        if (bon) xcur = x;
+                        xlay[u & 1][lane] = yval;
+                    } else {
+                        // ---- F: tick kf = k - 1 of the forward pass of strip i ----
+                        const int kf = k - 1;
+                        const bool fon = pf && kf >= 1 && kf <= n;
+                        const bool fin_on = pf && kf >= 0 && kf < n;
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
+                            colf[(u + 1) & 1][idx] = rk[u][c];
+                        }
+                        xfx[q][r] = z;
+                        wave_sync();
+                        const chunk16* cc = colf[(u + 1) & 1];     // column kf
+                        const chunk16* cprev = colf[u & 1];       // column kf - 1
+                        const CT wf = rowdot(cprev, xfx);          // w_{kf-1}
+                        gst(fon ? spw + (int64_t)(kf - 1) * 64 : (HS_GLOBAL CT*)dummy, wf);
+                        if (fon) {
+#pragma unroll
+                            for (int j = D - 1; j >= 1; --j) wlag[j] = wlag[j - 1];
+                            wlag[0] = wf;
+                            w = wf;
+                            if (kf == n) {
+#pragma unroll
+                                for (int j = 0; j < D; ++j) whand[j][lane] = wlag[j];   // w_{n-1-j}
+                            }
+                        }
+                        if (fin_on) {
+                            const CT ypart = xlay[(u + 1) & 1][lane];   // B's output of step k-1 = tick kf
+                            CT g = mk<T>(0, 0);
+                            if (MODE == MODE_FWD) {
+                                CT gv = ccast<T, double>(ra[u]);
+                                if (!full_f) gv = csub<T>(gv, cmul<T>(colscalar(cc, XCOL_APREV), ypart));
+                                g = (full_f ? act : slot) ? gv : mk<T>(0, 0);
+                            } else {
+                                g = slot ? cmul<T>(colscalar(cc, XCOL_ANEXT), i == 0 ? ccast<T, double>(ra[u]) : ypart)
+                                         : mk<T>(0, 0);
+                            }
+                            z = kf == 0 ? g : cfms<T>(cmul<T>(colscalar(cprev, XCOL_E), is2f), w, g);
+                        }
+                    }
+                    // F's workspace store above is issued before this step's ring loads (the compiler
+                    // must not hoist them): completing those loads then implies the store completed
+                    wave_sync();
+                    prefetch(u);
+                    step_barrier();
+                });
+                prefetch_next_group();
+            }
+        }
+    };
+    if (role == 0) run(std::integral_constant<int, 0>{});
+    else run(std::integral_constant<int, 1>{});
+}
+
+template <class T, class TF, class TI, class TO, int BV, int MODE>
+static bool sweep2_bs(int ks, const ProbDev* probs, const ChainDev* chains, int nblocks, const IoDev* io, IoDev iov,
+                      C2<T>* sp, hipStream_t s) {
+    constexpr int Q = RowsOf<BV>::Q, DV = Ring<T, BV>::D;
+    dim3 g(nblocks), b(128);
+    if (ks == 1) {
+        hipLaunchKernelGGL((k_sweep2<T, TF, TI, TO, BV, MODE, DV, 1>), g, b, 0, s, probs, chains, io, iov, sp);
+        return true;
+    }
+    if constexpr (Q >= 4) {
+        if (ks == 2) {
+            hipLaunchKernelGGL((k_sweep2<T, TF, TI, TO, BV, MODE, DV, 2>), g, b, 0, s, probs, chains, io, iov, sp);
+            return true;
+        }
+    }
+    if constexpr (Q >= 2) {
+        if (ks == Q) {
+            hipLaunchKernelGGL((k_sweep2<T, TF, TI, TO, BV, MODE, DV, Q>), g, b, 0, s, probs, chains, io, iov, sp);
+            return true;
+        }
+    }
+    return false;
+}
+
+template <class T, class TF, class TI, class TO, int MODE>
+static bool sweep2_typed(int bs, int ks, const ProbDev* probs, const ChainDev* chains, int nblocks, const IoDev* io,
+                         IoDev iov, void* spill, hipStream_t s) {
+    C2<T>* sp = (C2<T>*)spill;
+    switch (bs) {
+#define HS_CASE(BV) \
+    case BV: return sweep2_bs<T, TF, TI, TO, BV, MODE>(ks, probs, chains, nblocks, io, iov, sp, s);
+        HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13) HS_CASE(17)
+#undef HS_CASE
+        default: return false;
+    }
+}
+
+template <int MODE>
+static bool sweep2_prec(int bs, int ks, int prec, int in_prec, int out_prec, const ProbDev* probs,
+                        const ChainDev* chains, int nb, const IoDev* io, IoDev iov, void* spill, hipStream_t s) {
+    if (prec == 0) {
+        if (in_prec == 0 && out_prec == 0)
+            return sweep2_typed<double, double, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, s);
+        return false;
+    }
+    if (in_prec == 0 && out_prec == 0)
+        return sweep2_typed<float, float, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, s);
+    if (in_prec == 0 && out_prec == 1)
+        return sweep2_typed<float, float, double2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, s);
+    if (in_prec == 1 && out_prec == 1)
+        return sweep2_typed<float, float, float2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, s);
+    return false;
+}
+
+bool launch_chains2(int B, int prec, int in_prec, int out_prec, int phase, int ksplit, const ProbDev* probs,
+                    const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
+    if (nchains <= 0) return true;
+    return phase == 0 ? sweep2_prec<MODE_FWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, spill, s)
+                      : sweep2_prec<MODE_BWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, spill, s);
+}
+
+}  // namespace hs

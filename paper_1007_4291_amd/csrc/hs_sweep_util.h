@@ -1,0 +1,71 @@
+// Definitions shared by the sweep kernels (a3 / a4): compile-time loops, stored-column chunks,
+// conversions, lane sums and the prefetch depth.
+#pragma once
+
+#include <utility>
+
+#include "hs_common.h"
+#include "hs_kernels.h"
+
+namespace hs {
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N-1>): a loop unrolled at compile time
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F> __device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+enum SweepMode : int { MODE_FWD = 0, MODE_BWD = 1, MODE_MID = 2, MODE_SUB = 3 };
+
+// 16-byte chunk of a stored factor column (native vector type, kept in registers by the compiler)
+typedef unsigned int chunk16 __attribute__((ext_vector_type(4)));
+
+template <class TF, int BS> struct ColChunks {
+    static constexpr int STRIDE = col_stride<TF>(BS);
+    static constexpr int N16 = STRIDE * (int)sizeof(C2<TF>) / 16;   // 16-byte chunks per column
+    static constexpr int NCH = (N16 + 63) / 64;                      // chunks per lane
+};
+
+__device__ __forceinline__ double2 ld2(const HS_GLOBAL double2* p) { return gld(p); }
+__device__ __forceinline__ double2 ld2(const HS_GLOBAL float2* p) { const float2 v = gld(p); return make_double2(v.x, v.y); }
+template <class TO, class T> __device__ __forceinline__ TO cvt_out(C2<T> v);
+template <> __device__ __forceinline__ double2 cvt_out<double2, double>(double2 v) { return v; }
+template <> __device__ __forceinline__ double2 cvt_out<double2, float>(float2 v) { return make_double2(v.x, v.y); }
+template <> __device__ __forceinline__ float2 cvt_out<float2, float>(float2 v) { return v; }
+template <> __device__ __forceinline__ float2 cvt_out<float2, double>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+
+struct SubArg {
+    const void* fac;
+    const double2* g;
+    double2* x;
+    const double2* ris2;    // 1/s2 of local row r at ris2[rstep * r]
+    int nrhs, rstep, cdir, jl;
+};
+
+// Sum of v over lanes l and l ^ OFF (OFF = 16 or 32), in every lane, with the gfx950 row / half-wave
+// swap instructions (no LDS round trip).
+template <int OFF> __device__ __forceinline__ float xor_sum(float v) {
+    const unsigned b = __float_as_uint(v);
+    const auto s = OFF == 16 ? __builtin_amdgcn_permlane16_swap(b, b, false, false)
+                             : __builtin_amdgcn_permlane32_swap(b, b, false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+template <int OFF> __device__ __forceinline__ double xor_sum(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    const auto sl = OFF == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                              : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto sh = OFF == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                              : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const double a = __longlong_as_double((long long)(((uint64_t)sh[0] << 32) | sl[0]));
+    const double c = __longlong_as_double((long long)(((uint64_t)sh[1] << 32) | sl[1]));
+    return a + c;
+}
+
+// prefetch distance in ticks: as deep as the register budget of one wave allows
+template <class T, int BS> struct Ring { static constexpr int D = (sizeof(T) == 8 || BS > 17) ? 2 : 4; };
+
+}  // namespace hs

@@ -294,13 +294,15 @@ def test_batch_refactor_equals_individual(hs, torch, prec):
         assert np.array_equal(u, u0)
 
 
+@pytest.mark.parametrize("waves", [1, 2])
 @pytest.mark.parametrize("ks", [1, 2, 4])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_sweep_ksplit_parity(hs, torch, monkeypatch, ks, prec):
-    """Every right-hand-side grouping of the sweep waves (row-dot products split 1, 2 or 4 ways)
-    gives the oracle's M f, for a single problem and for an uneven batch."""
+def test_sweep_ksplit_parity(hs, torch, monkeypatch, ks, prec, waves):
+    """Every right-hand-side grouping of the sweep waves (row-dot products split 1, 2 or 4 ways), with
+    one or two waves per chain, gives the oracle's M f, for a single problem and for an uneven batch."""
     monkeypatch.setenv("HELM_SWEEP_KSPLIT", str(ks))
-    _log("ksplit", ks, "prec", prec)
+    monkeypatch.setenv("HELM_SWEEP_WAVES", str(waves))
+    _log("ksplit", ks, "prec", prec, "waves", waves)
     op, c = _case("cfg1")
     A = _gpu_problem(hs, torch, op, c)
     F = hs.Factors(A, prec)
