@@ -45,7 +45,7 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
     __shared__ CT xbx[Q][RP];            // B: exchange vector
     __shared__ CT xfx[Q][RP];            // F: exchange vector
     __shared__ CT xlay[2][64];           // B -> F: layer output, by step parity
-    __shared__ CT whand[D][64];          // F -> B: forward products of the last D steps of a strip
+    __shared__ CT wring[2][D][64];       // F -> B: last D forward products of a strip, by pair parity
 
     const int role = threadIdx.x >> 6;   // 0: backward pass (B), 1: forward pass (F); wave-uniform
     const int lane = threadIdx.x & 63, r = lane % RP, q = lane / RP;
@@ -132,7 +132,19 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
     };
 
     // Each role runs its own loop nest (its own prefetch sequence, so the compiler's waits cover
-    // exactly the loads of one group earlier); both execute one barrier per step.
+    // exactly the loads of one group earlier); both execute one barrier per step.  Factor columns and
+    // the workspace are read and written through buffer resources (per-lane offset in a register,
+    // per-step offset scalar).
+    const __amdgpu_buffer_rsrc_t srs = buf_rsrc(spill, (uint32_t)(chain_spill_elems(n) * sizeof(CT)));
+    const uint32_t lane_cb = (uint32_t)(lane * sizeof(CT));
+    const uint32_t ws_bytes = (uint32_t)(64 * sizeof(CT));               // one workspace step
+    const uint32_t dummy_off = (uint32_t)(2 * n) * ws_bytes;             // the slot after the workspace
+    const uint32_t strip_bytes = (uint32_t)(n * colbytes);
+    uint32_t chunk_off[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) chunk_off[c] = (uint32_t)(c * 64 + lane < N16 ? c * 64 + lane : N16 - 1) * 16u;
+    const int nmod = (n - 1) % D;
+
     auto run = [&](auto RC) __attribute__((always_inline)) {
         constexpr int ROLE = decltype(RC)::value;
         // register ring: the column of this wave's strip; B: workspace value and (backward phase)
@@ -144,8 +156,8 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
         // Prefetch cursor (step pk of pair pi), one group ahead.  B at step pk needs tick pk of pair
         // pi, F tick pk - 1.  Positions outside a strip are clamped to valid memory (values unused).
         int pi = 0, pg = 0, pdir = 1;
-        const HS_GLOBAL char* pcol = facbase;   // B: column n-1 of strip pi-1; F: column 0 of strip pi
-        const HS_GLOBAL CT* psp = spill;        // B: workspace of strip pi-1 at step n-1
+        __amdgpu_buffer_rsrc_t pcr = buf_rsrc(facbase, strip_bytes);   // B: strip pi-1; F: strip pi
+        uint32_t psp = 0;                       // B: workspace byte offset of strip pi-1, step 0
         const HS_GLOBAL TI* pfrow = fin;        // F, forward phase: input row of strip pi
         const HS_GLOBAL TO* pyrow = y;          // B, backward phase: output row of strip pi-1
         auto pset = [&]() __attribute__((always_inline)) {
@@ -153,11 +165,11 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
             const int ib = pc >= 1 ? pc - 1 : 0, ifw = pc <= m ? pc : m;
             pdir = strip_dir(pc);
             if constexpr (ROLE == 0) {
-                pcol = strip_fac(ib) + colbytes * (n - 1);
-                psp = spill + (int64_t)(ib & 1) * n * 64 + (int64_t)(n - 1) * 64 + lane;
+                pcr = buf_rsrc(strip_fac(ib), strip_bytes);
+                psp = (uint32_t)((ib & 1) * n) * ws_bytes;
                 if (MODE == MODE_BWD) pyrow = y + (int64_t)(strip_row(ib, strip_full(ib)) - 1) * n;
             } else {
-                pcol = strip_fac(ifw);
+                pcr = buf_rsrc(strip_fac(ifw), strip_bytes);
                 if (MODE == MODE_FWD) pfrow = fin + (int64_t)(strip_row(ifw, strip_full(ifw)) - 1) * n;
             }
         };
@@ -167,18 +179,18 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
             if constexpr (ROLE == 0) {
                 const int k2 = pk < n ? pk : n - 1;
                 const int col = pdir > 0 ? k2 + 1 : n - k2;
-                const HS_GLOBAL chunk16* src = (const HS_GLOBAL chunk16*)(pcol - colbytes * k2);
+                const uint32_t coff = (uint32_t)(n - 1 - k2) * (uint32_t)colbytes;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) rk[u][c] = src[c * 64 + lane < N16 ? c * 64 + lane : N16 - 1];
-                rsp[u] = gld(psp - (int64_t)k2 * 64);
+                for (int c = 0; c < NCH; ++c) rk[u][c] = buf_ld16(pcr, chunk_off[c], coff);
+                buf_ld(rsp[u], srs, lane_cb, psp + (uint32_t)(n - 1 - k2) * ws_bytes);
                 if (MODE == MODE_BWD) ra[u] = ld2(pyrow + col - 1);
             } else {
                 const int kf = pk - 1;
                 const int k2 = kf < 0 ? 0 : (kf < n ? kf : n - 1);
                 const int col = pdir > 0 ? k2 + 1 : n - k2;
-                const HS_GLOBAL chunk16* src = (const HS_GLOBAL chunk16*)(pcol + colbytes * k2);
+                const uint32_t coff = (uint32_t)k2 * (uint32_t)colbytes;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) rk[u][c] = src[c * 64 + lane < N16 ? c * 64 + lane : N16 - 1];
+                for (int c = 0; c < NCH; ++c) rk[u][c] = buf_ld16(pcr, chunk_off[c], coff);
                 if (MODE == MODE_FWD) ra[u] = ld2(pfrow + col - 1);
                 else ra[u] = ld2(y + (int64_t)(cmid - 1) * n + col - 1);
             }
@@ -189,11 +201,8 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
         static_for<D>([&](auto UC) __attribute__((always_inline)) { prefetch(decltype(UC)::value); });
         prefetch_next_group();
 
-        // B: previous layer-row value; F: z, last forward product, the last D products
+        // B: previous layer-row value; F: z and the last forward product
         CT xcur = mk<T>(0, 0), z = mk<T>(0, 0), w = mk<T>(0, 0);
-        CT wlag[D];
-#pragma unroll
-        for (int j = 0; j < D; ++j) wlag[j] = mk<T>(0, 0);
 
         for (int i = 0; i <= m + 1; ++i) {
             const bool pb = i >= 1, pf = i <= m;
@@ -205,7 +214,7 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
             const bool wy = pb && (full_b ? own : oslot);
             const bool full_f = strip_full(ifw);
             const CT is2f = strip_is2(ifw);
-            HS_GLOBAL CT* const spw = spill + (int64_t)(i & 1) * n * 64 + lane;
+            const uint32_t spw = (uint32_t)((i & 1) * n) * ws_bytes;    // F: workspace of strip i
 
             for (int kb = 0; kb < G; ++kb) {
                 static_for<D>([&](auto UC) __attribute__((always_inline)) {
@@ -222,7 +231,9 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
                         }
                         xbx[q][r] = cmul<T>(is2b, xcur);
                         wave_sync();
-                        const CT ws = kb == 0 ? whand[u][lane] : rsp[u];   // first group: handed over in LDS
+                        // first group: w_{n-1-u} of strip i-1 from the ring of the previous pair
+                        const CT wr = wring[(i + 1) & 1][(nmod - u + D) % D][lane];
+                        const CT ws = kb == 0 ? wr : rsp[u];
                         const CT xb = cfms<T>(colscalar(colb, XCOL_E), rowdot(colb, xbx), ws);
                         const CT x = k == 0 ? ws : xb;
                         const CT yval = MODE == MODE_BWD ? csub<T>(ccast<T, double>(ra[u]), x) : x;
@@ -244,16 +255,10 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
                         const chunk16* cc = colf[(u + 1) & 1];     // column kf
                         const chunk16* cprev = colf[u & 1];       // column kf - 1
                         const CT wf = rowdot(cprev, xfx);          // w_{kf-1}
-                        gst(fon ? spw + (int64_t)(kf - 1) * 64 : (HS_GLOBAL CT*)dummy, wf);
+                        buf_st(wf, srs, lane_cb, fon ? spw + (uint32_t)(kf - 1) * ws_bytes : dummy_off);
                         if (fon) {
-#pragma unroll
-                            for (int j = D - 1; j >= 1; --j) wlag[j] = wlag[j - 1];
-                            wlag[0] = wf;
                             w = wf;
-                            if (kf == n) {
-#pragma unroll
-                                for (int j = 0; j < D; ++j) whand[j][lane] = wlag[j];   // w_{n-1-j}
-                            }
+                            wring[i & 1][(u + D - 2) % D][lane] = wf;    // slot (kf - 1) mod D
                         }
                         if (fin_on) {
                             const CT ypart = xlay[(u + 1) & 1][lane];   // B's output of step k-1 = tick kf

@@ -65,6 +65,35 @@ template <int OFF> __device__ __forceinline__ double xor_sum(double v) {
     return a + c;
 }
 
+// Raw buffer access: a wave-uniform resource (base, size in bytes) plus a per-lane byte offset in a
+// VGPR and a wave-uniform byte offset in an SGPR, so per-step address arithmetic stays scalar.
+typedef unsigned int hs_u2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const HS_GLOBAL void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)base, (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ chunk16 buf_ld16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_ld(float2& v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const hs_u2 b = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    v = make_float2(__uint_as_float(b.x), __uint_as_float(b.y));
+}
+__device__ __forceinline__ void buf_ld(double2& v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const chunk16 b = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    v = make_double2(__hiloint2double((int)b.y, (int)b.x), __hiloint2double((int)b.w, (int)b.z));
+}
+__device__ __forceinline__ void buf_st(float2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    hs_u2 b;
+    b.x = __float_as_uint(v.x); b.y = __float_as_uint(v.y);
+    __builtin_amdgcn_raw_buffer_store_b64(b, r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st(double2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const uint64_t a = (uint64_t)__double_as_longlong(v.x), c = (uint64_t)__double_as_longlong(v.y);
+    chunk16 b;
+    b.x = (unsigned)a; b.y = (unsigned)(a >> 32); b.z = (unsigned)c; b.w = (unsigned)(c >> 32);
+    __builtin_amdgcn_raw_buffer_store_b128(b, r, (int)voff, (int)soff, 0);
+}
+
 // prefetch distance in ticks: as deep as the register budget of one wave allows
 template <class T, int BS> struct Ring { static constexpr int D = (sizeof(T) == 8 || BS > 17) ? 2 : 4; };
 
