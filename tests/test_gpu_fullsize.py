@@ -1,0 +1,182 @@
+"""Parity at the full sizes of the workloads, through the C-ABI (GPU).
+
+At these sizes the oracle cannot run everything, so each test combines
+  * outputs the oracle computes one by one: the matvec, single strip solves (one strip factored
+    with LAPACK's band LU), one full preconditioner application where the oracle finishes in
+    seconds (n = 1023);
+  * properties that hold at any size: every solution's true FP64 relative residual, computed with
+    the oracle's independently assembled operator, is at most the requested 1e-6.
+The batched test runs the exact workload and launch configuration that bench.py times.
+Tolerances as in test_gpu_parity: complex64 strip solves 2e-5, complex64 sweep 1e-4, matvec 1e-14.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import helmholtz as OH
+from oracle import krylov as OK
+from oracle import sweep as OS
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def hs():
+    from paper_1007_4291_amd import helmsweep
+    return helmsweep
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    return torch
+
+
+def _params(p):
+    return OH.Params(n=p.n, omega=p.omega, alpha=p.alpha, pml_w=p.pml_w, mpml_w=p.mpml_w)
+
+
+def _gpu(hs, torch, p):
+    gp = hs.Params(n=p.n, omega=p.omega, alpha=p.alpha, pml_w=p.pml_w, mpml_w=p.mpml_w)
+    return hs.Problem(gp, torch.as_tensor(p.c, dtype=torch.float64, device="cuda"))
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _true_relres(Ao, f, u):
+    """Per right-hand side ||f - A u|| / ||f|| with the oracle's sparse A (FP64)."""
+    r = f.T - Ao @ u.T
+    return np.linalg.norm(r, axis=0) / np.linalg.norm(f, axis=1)
+
+
+def _strip_spec(op, specs, sub):
+    L_lo = op.mid - 1 - op.B
+    nsub = len(specs["lower"]) + len(specs["upper"]) + 3
+    if sub == 0:
+        return specs["F"], False
+    if sub <= L_lo:
+        return specs["lower"][sub - 1], False
+    if sub == L_lo + 1:
+        return specs["E"], True
+    if sub == nsub - 1:
+        return specs["mid"], False
+    return specs["upper"][sub - L_lo - 2], True
+
+
+def _check_matvec(hs, torch, A, Ao, n, seed):
+    x = workloads.random_rhs(n, 2, seed=seed)
+    y = A.matvec(torch.as_tensor(x, device="cuda")).cpu().numpy()
+    err = _rel(y, (Ao @ x.T).T)
+    _log(f"  matvec rel {err:.2e}")
+    assert err <= 1e-14
+
+
+def _check_strips(hs, torch, op, c, F, tol, seed):
+    """Sampled strips (front block, first and middle moving layers of each front, middle strip):
+    the GPU's block LU solve against LAPACK's band LU of the same strip."""
+    specs = OS.subproblem_specs(op)
+    L_lo = op.mid - 1 - op.B
+    nsub = F.num_subproblems
+    picks = sorted(set([0, 1, L_lo // 2, L_lo + 1, L_lo + 2, nsub - 2, nsub - 1]))
+    rng = np.random.default_rng(seed)
+    for sub in picks:
+        spec, flip = _strip_spec(op, specs, sub)
+        band = OS.band_factor(op, c, spec)
+        R = F.subproblem_rows(sub)
+        assert R == band.R
+        g = rng.standard_normal((2, R, op.n)) + 1j * rng.standard_normal((2, R, op.n))
+        x = F.subsolve(sub, torch.as_tensor(g, device="cuda")).cpu().numpy()
+        go = g[:, ::-1, :] if flip else g
+        xo = np.transpose(band.solve_rows(np.ascontiguousarray(np.transpose(go, (1, 2, 0)))), (2, 0, 1))
+        if flip:
+            xo = xo[:, ::-1, :]
+        err = _rel(x, xo)
+        _log(f"  strip {sub} rows {R}: rel {err:.2e}")
+        assert err <= tol
+
+
+def test_grf1023_mixed_fullsize(hs, torch):
+    """n = 1023, omega/2pi = 128, Gaussian random velocity, complex64 factors and sweep under FP64
+    FGMRES(20): matvec, sampled strips and one whole preconditioner application against the oracle;
+    the solve reaches a true residual of 1e-6; error against the FP64 GPU solve reported."""
+    p = workloads.cfg3()
+    op = _params(p)
+    _log("grf1023: n", p.n)
+    A = _gpu(hs, torch, p)
+    Ao = OH.assemble(op, p.c, shifted=False)
+    _check_matvec(hs, torch, A, Ao, p.n, seed=31)
+    F = hs.Factors(A, hs.HELM_C64)
+    _check_strips(hs, torch, op, p.c, F, 2e-5, seed=32)
+    Mo = OS.factor(op, p.c)
+    f1 = p.f[:1]
+    u = F.apply(torch.as_tensor(f1, device="cuda").to(torch.complex64)).cpu().numpy().astype(np.complex128)
+    uo = OS.apply_sweep(Mo, f1.astype(np.complex64).astype(np.complex128))
+    err = _rel(u, uo)
+    _log(f"  sweep apply (complex64) rel {err:.2e}")
+    assert err <= 1e-4
+    fd = torch.as_tensor(p.f, device="cuda")
+    res = hs.fgmres(A, F, fd, restart=p.restart, tol=p.tol, maxit=400)
+    rr = _true_relres(Ao, p.f, res.u.cpu().numpy())
+    F64 = hs.Factors(A, hs.HELM_C128)
+    res64 = hs.fgmres(A, F64, fd, restart=p.restart, tol=p.tol, maxit=400)
+    e64 = _rel(res.u.cpu().numpy(), res64.u.cpu().numpy())
+    _log(f"  fgmres iters {res.iters} (fp64 {res64.iters}); true relres {rr.max():.3e}; error vs fp64 solve {e64:.2e}")
+    assert res.converged and rr.max() <= 1e-6 * (1 + 1e-6)
+
+
+def test_batched96_fullsize(hs, torch):
+    """The batched uneven workload exactly as bench.py times it (96 problems, n in {127, 255, 511},
+    8 point sources each, complex64 factors, batched FGMRES(20) to 1e-6): every system's true
+    residual is at most 1e-6, and a sampled problem's solutions match the oracle's FGMRES."""
+    probs = workloads.cfg4()
+    _log("batched96:", len(probs), "problems")
+    A = [_gpu(hs, torch, p) for p in probs]
+    M = [hs.Factors(a, hs.HELM_C64) for a in A]
+    b = hs.Batch(A, M, [p.nrhs for p in probs], restart=probs[0].restart)
+    b.refactor()
+    f = [torch.as_tensor(p.f, device="cuda") for p in probs]
+    res = b.solve(f, tol=probs[0].tol, maxit=400)
+    assert res.converged
+    worst = 0.0
+    for p, u in zip(probs, res.u):
+        Ao = OH.assemble(_params(p), p.c, shifted=False)
+        worst = max(worst, float(_true_relres(Ao, p.f, u.cpu().numpy()).max()))
+    _log(f"  iters {min(res.iters)}-{max(res.iters)}; worst true relres {worst:.3e}")
+    assert worst <= 1e-6 * (1 + 1e-6)
+    # sampled problem: the first one (n = 127), all 8 right-hand sides, against the oracle
+    p = probs[0]
+    op = _params(p)
+    Ao = OH.assemble(op, p.c, shifted=False)
+    Mo = OS.factor(op, p.c)
+    u = res.u[0].cpu().numpy()
+    for q in range(p.nrhs):
+        ro = OK.fgmres(lambda v: Ao @ v, lambda v: OS.apply_sweep(Mo, v), p.f[q], p.restart, p.tol)
+        err = _rel(u[q], ro.x)
+        assert err <= 1e-6, (q, err)
+    _log("  sampled problem matches the oracle to 1e-6")
+
+
+def test_waveguide2047_fullsize(hs, torch):
+    """n = 2047, omega/2pi = 256, waveguide velocity, widths 16 (strips of 17 rows, middle 33):
+    matvec and sampled strips against the oracle; FGMRES(30) with complex64 factors on 8 of the 64
+    sources (every eighth, at their own positions) reaches a true residual of 1e-6."""
+    p = workloads.cfg5(pick=slice(0, 64, 8))
+    op = _params(p)
+    _log("waveguide2047: n", p.n, "rhs", p.nrhs)
+    A = _gpu(hs, torch, p)
+    Ao = OH.assemble(op, p.c, shifted=False)
+    _check_matvec(hs, torch, A, Ao, p.n, seed=51)
+    F = hs.Factors(A, hs.HELM_C64)
+    _check_strips(hs, torch, op, p.c, F, 2e-5, seed=52)
+    res = hs.fgmres(A, F, torch.as_tensor(p.f, device="cuda"), restart=p.restart, tol=p.tol, maxit=400)
+    rr = _true_relres(Ao, p.f, res.u.cpu().numpy())
+    _log(f"  fgmres iters {res.iters}; true relres {rr.max():.3e}")
+    assert res.converged and rr.max() <= 1e-6 * (1 + 1e-6)

@@ -196,11 +196,15 @@ def cfg4(per_size: int = 32, sizes=(127, 255, 511), nsrc: int = 8) -> List[Probl
     return [cfg4_problem(n, k, nsrc) for n in sizes for k in range(per_size)]
 
 
-def cfg5(n: int = 2047, freq: float = 256.0, nsrc: int = 64, width: int = 16) -> Problem:
-    """2047x2047 waveguide, 64 point sources along x2 = 0.1, widths 16, FGMRES(30)."""
+def cfg5(n: int = 2047, freq: float = 256.0, nsrc: int = 64, width: int = 16, pick=None) -> Problem:
+    """2047x2047 waveguide, 64 point sources along x2 = 0.1, widths 16, FGMRES(30).
+
+    ``pick`` (a slice or index list) keeps only some of the nsrc sources, at their own positions."""
     B = width + 1
     j0 = int(round(0.1 * (n + 1)))
     ii = np.rint(np.linspace(B + 1, n - B, nsrc)).astype(int)
+    if pick is not None:
+        ii = ii[pick]
     f = np.stack([source_point(n, int(i), j0) for i in ii])
     return Problem(f"cfg5_waveguide_n{n}", n, 2 * math.pi * freq, width, width,
                    velocity_waveguide(n, seed_for(5)), f, restart=30)
