@@ -129,8 +129,6 @@ def sweep_bytes_flops(probs, B, fac_bytes, vin, vout):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_chains_batched96_c64_traffic.json")
-TRAFFIC_SOURCES = ["paper_1007_4291_amd/csrc/hs_sweep.hip", "paper_1007_4291_amd/csrc/hs_common.h",
-                   "paper_1007_4291_amd/csrc/hs_kernels.h", "paper_1007_4291_amd/csrc/hs_api.cpp"]
 
 
 def measured_traffic(workload, prec_name):
@@ -143,7 +141,7 @@ def measured_traffic(workload, prec_name):
     with open(TRAFFIC_FILE) as fh:
         tr = json.load(fh)
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in tr.get("source_files", []):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return tr["traffic_bytes_per_launch"] if h.hexdigest() == tr.get("source_sha256") else None
