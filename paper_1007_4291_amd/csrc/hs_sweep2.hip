@@ -51,6 +51,7 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
     const int lane = threadIdx.x & 63, r = lane % RP, q = lane / RP;
     const int rq = q / KS, kg = q % KS;
     constexpr int KMAX = (BS + KS - 1) / KS;
+    static_assert(BS + KS - 1 <= RP, "the k-split's last round must stay inside the padded rows");
     const ChainDev ch = chains[blockIdx.x];
     const ProbDev& P = probs[ch.prob];
     const IoDev IO = io ? io[ch.prob] : io_val;
@@ -115,10 +116,11 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
         CT acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
 #pragma unroll
         for (int jj = 0; jj < KMAX; ++jj) {
+            // k >= BS only in the last round of a k-split: the exchange entry there is a zero
+            // padding row and the factor offset is clamped to a valid entry
             const int k = kg + KS * jj;
             const CT l = ccast<T, TF>(cf[loff[jj]]);
-            const CT xk = xv[q][KS == 1 ? jj : (k < BS ? k : 0)];
-            const CT t = (KS == 1 || k < BS) ? xk : mk<T>(0, 0);
+            const CT t = xv[q][KS == 1 ? jj : k];
             if (jj & 1) acc1 = cfma<T>(l, t, acc1);
             else acc0 = cfma<T>(l, t, acc0);
         }
@@ -153,56 +155,75 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
         CT rsp[D];
         double2 ra[D];
 
-        // Prefetch cursor (step pk of pair pi), one group ahead.  B at step pk needs tick pk of pair
-        // pi, F tick pk - 1.  Positions outside a strip are clamped to valid memory (values unused).
-        int pi = 0, pg = 0, pdir = 1;
-        __amdgpu_buffer_rsrc_t pcr = buf_rsrc(facbase, strip_bytes);   // B: strip pi-1; F: strip pi
-        uint32_t psp = 0;                       // B: workspace byte offset of strip pi-1, step 0
-        const HS_GLOBAL TI* pfrow = fin;        // F, forward phase: input row of strip pi
-        const HS_GLOBAL TO* pyrow = y;          // B, backward phase: output row of strip pi-1
-        auto pset = [&]() __attribute__((always_inline)) {
+        // Prefetch sources of pair pi (B: strip pi-1, F: strip pi), computed once per pair.  Column
+        // and workspace reads past a strip's ends are not clamped: their offset, carried in the
+        // per-lane (range-checked) buffer offset, falls outside the resource and reads zeros, or
+        // hits workspace entries whose values are never used.  Input rows are plain global loads
+        // and clamp their column.
+        struct Src {
+            __amdgpu_buffer_rsrc_t col;
+            uint32_t sp;                 // B: workspace byte offset of strip pi-1
+            const HS_GLOBAL TI* frow;    // F, forward phase: input row of strip pi
+            const HS_GLOBAL TO* yrow;    // B, backward phase: output row of strip pi-1
+            int dir;
+        };
+        auto src_of = [&](int pi) __attribute__((always_inline)) -> Src {
             const int pc = pi <= m + 1 ? pi : m + 1;
             const int ib = pc >= 1 ? pc - 1 : 0, ifw = pc <= m ? pc : m;
-            pdir = strip_dir(pc);
+            Src S;
+            S.dir = strip_dir(pc);
+            S.frow = fin;
+            S.yrow = y;
+            S.sp = 0;
             if constexpr (ROLE == 0) {
-                pcr = buf_rsrc(strip_fac(ib), strip_bytes);
-                psp = (uint32_t)((ib & 1) * n) * ws_bytes;
-                if (MODE == MODE_BWD) pyrow = y + (int64_t)(strip_row(ib, strip_full(ib)) - 1) * n;
+                S.col = buf_rsrc(strip_fac(ib), strip_bytes);
+                S.sp = (uint32_t)((ib & 1) * n) * ws_bytes;
+                if (MODE == MODE_BWD) S.yrow = y + (int64_t)(strip_row(ib, strip_full(ib)) - 1) * n;
             } else {
-                pcr = buf_rsrc(strip_fac(ifw), strip_bytes);
-                if (MODE == MODE_FWD) pfrow = fin + (int64_t)(strip_row(ifw, strip_full(ifw)) - 1) * n;
+                S.col = buf_rsrc(strip_fac(ifw), strip_bytes);
+                if (MODE == MODE_FWD) S.frow = fin + (int64_t)(strip_row(ifw, strip_full(ifw)) - 1) * n;
             }
+            return S;
         };
-        pset();
-        auto prefetch = [&](int u) __attribute__((always_inline)) {
-            const int pk = pg * D + u;
+        // ring slot u for step pk of the pair described by S (B: tick pk; F: tick pk - 1); CL: the
+        // step may lie outside the strip (clamp the input-row column)
+        auto prefetch = [&](const Src& S, int pk, int u, auto CLC) __attribute__((always_inline)) {
+            constexpr bool CL = decltype(CLC)::value;
             if constexpr (ROLE == 0) {
-                const int k2 = pk < n ? pk : n - 1;
-                const int col = pdir > 0 ? k2 + 1 : n - k2;
-                const uint32_t coff = (uint32_t)(n - 1 - k2) * (uint32_t)colbytes;
+                const uint32_t back = (uint32_t)(n - 1 - pk);
+                const uint32_t coff = back * (uint32_t)colbytes;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) rk[u][c] = buf_ld16(pcr, chunk_off[c], coff);
-                buf_ld(rsp[u], srs, lane_cb, psp + (uint32_t)(n - 1 - k2) * ws_bytes);
-                if (MODE == MODE_BWD) ra[u] = ld2(pyrow + col - 1);
+                for (int c = 0; c < NCH; ++c) rk[u][c] = buf_ld16(S.col, chunk_off[c] + coff, 0);
+                buf_ld(rsp[u], srs, lane_cb + S.sp + back * ws_bytes, 0);
+                if (MODE == MODE_BWD) {
+                    const int k2 = CL ? (pk < n - 1 ? pk : n - 1) : pk;
+                    const int col = S.dir > 0 ? k2 + 1 : n - k2;
+                    ra[u] = ld2(S.yrow + col - 1);
+                }
             } else {
-                const int kf = pk - 1;
-                const int k2 = kf < 0 ? 0 : (kf < n ? kf : n - 1);
-                const int col = pdir > 0 ? k2 + 1 : n - k2;
-                const uint32_t coff = (uint32_t)k2 * (uint32_t)colbytes;
+                const uint32_t coff = (uint32_t)(pk - 1) * (uint32_t)colbytes;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) rk[u][c] = buf_ld16(pcr, chunk_off[c], coff);
-                if (MODE == MODE_FWD) ra[u] = ld2(pfrow + col - 1);
+                for (int c = 0; c < NCH; ++c) rk[u][c] = buf_ld16(S.col, chunk_off[c] + coff, 0);
+                const int k2 = CL ? max(0, min(pk - 1, n - 1)) : pk - 1;
+                const int col = S.dir > 0 ? k2 + 1 : n - k2;
+                if (MODE == MODE_FWD) ra[u] = ld2(S.frow + col - 1);
                 else ra[u] = ld2(y + (int64_t)(cmid - 1) * n + col - 1);
             }
         };
-        auto prefetch_next_group = [&]() __attribute__((always_inline)) {
-            if (++pg == G) { pg = 0; ++pi; pset(); }
-        };
-        static_for<D>([&](auto UC) __attribute__((always_inline)) { prefetch(decltype(UC)::value); });
-        prefetch_next_group();
+
+        Src cur = src_of(0), nxt = src_of(1);
+        static_for<D>([&](auto UC) __attribute__((always_inline)) {
+            constexpr int u = decltype(UC)::value;
+            prefetch(cur, u, u, std::integral_constant<bool, true>{});
+        });
 
         // B: previous layer-row value; F: z and the last forward product
         CT xcur = mk<T>(0, 0), z = mk<T>(0, 0), w = mk<T>(0, 0);
+        // Steady groups: all D ticks of the group and of the next one (which it prefetches) inside
+        // the strip, not the first group.  There no boundary condition applies: a wave without a
+        // strip in this pair (B in the first pair, F in the last) computes unused values, whose
+        // workspace and ring writes go to the parity its partner does not read in this pair.
+        const int kb_steady = (n - D) / D - 1;
 
         for (int i = 0; i <= m + 1; ++i) {
             const bool pb = i >= 1, pf = i <= m;
@@ -216,72 +237,91 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
             const CT is2f = strip_is2(ifw);
             const uint32_t spw = (uint32_t)((i & 1) * n) * ws_bytes;    // F: workspace of strip i
 
-            for (int kb = 0; kb < G; ++kb) {
-                static_for<D>([&](auto UC) __attribute__((always_inline)) {
-                    constexpr int u = decltype(UC)::value;
-                    const int k = kb * D + u;
-                    if constexpr (ROLE == 0) {
-                        // ---- B: tick k of the backward pass of strip i-1 (step s = n-1-k) ----
-                        const bool bon = pb && k < n;
-                        const int col = cd > 0 ? k + 1 : n - k;
+            // one step: tick k = kb*D + u of this pair (F: tick k-1); ST: steady group (all D ticks
+            // inside the strip, not the first group); the ring slot is then refilled for step pk of
+            // the pair described by PS
+            auto step = [&](auto UC, auto SC, int kb, const Src& PS, int pk) __attribute__((always_inline)) {
+                constexpr int u = decltype(UC)::value;
+                constexpr bool ST = decltype(SC)::value;
+                const int k = kb * D + u;
+                if constexpr (ROLE == 0) {
+                    // ---- B: tick k of the backward pass of strip i-1 (step s = n-1-k) ----
+                    const bool bon = ST ? pb : (pb && k < n);
+                    const int col = cd > 0 ? k + 1 : n - k;
 #pragma unroll
-                        for (int c = 0; c < NCH; ++c) {
-                            const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
-                            colb[idx] = rk[u][c];
-                        }
-                        xbx[q][r] = cmul<T>(is2b, xcur);
-                        wave_sync();
+                    for (int c = 0; c < NCH; ++c) {
+                        const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
+                        colb[idx] = rk[u][c];
+                    }
+                    xbx[q][r] = rok ? cmul<T>(is2b, xcur) : mk<T>(0, 0);   // padding rows read as zeros
+                    wave_sync();
+                    CT ws = rsp[u];
+                    if constexpr (!ST) {
                         // first group: w_{n-1-u} of strip i-1 from the ring of the previous pair
                         const CT wr = wring[(i + 1) & 1][(nmod - u + D) % D][lane];
-                        const CT ws = kb == 0 ? wr : rsp[u];
-                        const CT xb = cfms<T>(colscalar(colb, XCOL_E), rowdot(colb, xbx), ws);
-                        const CT x = k == 0 ? ws : xb;
-                        const CT yval = MODE == MODE_BWD ? csub<T>(ccast<T, double>(ra[u]), x) : x;
-                        gst((wy && bon) ? yrow + col - 1 : (HS_GLOBAL TO*)dummy, cvt_out<TO, T>(yval));
-                        if (bon) xcur = x;
-                        xlay[u & 1][lane] = yval;
-                    } else {
-                        // ---- F: tick kf = k - 1 of the forward pass of strip i ----
-                        const int kf = k - 1;
-                        const bool fon = pf && kf >= 1 && kf <= n;
-                        const bool fin_on = pf && kf >= 0 && kf < n;
-#pragma unroll
-                        for (int c = 0; c < NCH; ++c) {
-                            const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
-                            colf[(u + 1) & 1][idx] = rk[u][c];
-                        }
-                        xfx[q][r] = z;
-                        wave_sync();
-                        const chunk16* cc = colf[(u + 1) & 1];     // column kf
-                        const chunk16* cprev = colf[u & 1];       // column kf - 1
-                        const CT wf = rowdot(cprev, xfx);          // w_{kf-1}
-                        buf_st(wf, srs, lane_cb, fon ? spw + (uint32_t)(kf - 1) * ws_bytes : dummy_off);
-                        if (fon) {
-                            w = wf;
-                            wring[i & 1][(u + D - 2) % D][lane] = wf;    // slot (kf - 1) mod D
-                        }
-                        if (fin_on) {
-                            const CT ypart = xlay[(u + 1) & 1][lane];   // B's output of step k-1 = tick kf
-                            CT g = mk<T>(0, 0);
-                            if (MODE == MODE_FWD) {
-                                CT gv = ccast<T, double>(ra[u]);
-                                if (!full_f) gv = csub<T>(gv, cmul<T>(colscalar(cc, XCOL_APREV), ypart));
-                                g = (full_f ? act : slot) ? gv : mk<T>(0, 0);
-                            } else {
-                                g = slot ? cmul<T>(colscalar(cc, XCOL_ANEXT), i == 0 ? ccast<T, double>(ra[u]) : ypart)
-                                         : mk<T>(0, 0);
-                            }
-                            z = kf == 0 ? g : cfms<T>(cmul<T>(colscalar(cprev, XCOL_E), is2f), w, g);
-                        }
+                        ws = kb == 0 ? wr : ws;
                     }
-                    // F's workspace store above is issued before this step's ring loads (the compiler
-                    // must not hoist them): completing those loads then implies the store completed
+                    const CT xb = cfms<T>(colscalar(colb, XCOL_E), rowdot(colb, xbx), ws);
+                    const CT x = (!ST && k == 0) ? ws : xb;
+                    const CT yval = MODE == MODE_BWD ? csub<T>(ccast<T, double>(ra[u]), x) : x;
+                    gst((ST ? wy : (wy && bon)) ? yrow + col - 1 : (HS_GLOBAL TO*)dummy, cvt_out<TO, T>(yval));
+                    if (ST || bon) xcur = x;   // steady: unconditional (first pair: values unused)
+                    xlay[u & 1][lane] = yval;
+                } else {
+                    // ---- F: tick kf = k - 1 of the forward pass of strip i ----
+                    const int kf = k - 1;
+                    const bool fon = ST || (pf && kf >= 1 && kf <= n);
+                    const bool fin_on = ST || (pf && kf >= 0 && kf < n);
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+                        const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
+                        colf[(u + 1) & 1][idx] = rk[u][c];
+                    }
+                    xfx[q][r] = rok ? z : mk<T>(0, 0);
                     wave_sync();
-                    prefetch(u);
-                    step_barrier();
+                    const chunk16* cc = colf[(u + 1) & 1];     // column kf
+                    const chunk16* cprev = colf[u & 1];       // column kf - 1
+                    const CT wf = rowdot(cprev, xfx);          // w_{kf-1}
+                    buf_st(wf, srs, lane_cb, fon ? spw + (uint32_t)(kf - 1) * ws_bytes : dummy_off);
+                    if (fon) {
+                        w = wf;
+                        wring[i & 1][(u + D - 2) % D][lane] = wf;    // slot (kf - 1) mod D
+                    }
+                    if (fin_on) {
+                        const CT ypart = xlay[(u + 1) & 1][lane];   // B's output of step k-1 = tick kf
+                        CT g = mk<T>(0, 0);
+                        if (MODE == MODE_FWD) {
+                            CT gv = ccast<T, double>(ra[u]);
+                            if (!full_f) gv = csub<T>(gv, cmul<T>(colscalar(cc, XCOL_APREV), ypart));
+                            g = (full_f ? act : slot) ? gv : mk<T>(0, 0);
+                        } else {
+                            g = slot ? cmul<T>(colscalar(cc, XCOL_ANEXT), i == 0 ? ccast<T, double>(ra[u]) : ypart)
+                                     : mk<T>(0, 0);
+                        }
+                        const CT zn = cfms<T>(cmul<T>(colscalar(cprev, XCOL_E), is2f), w, g);
+                        z = (!ST && kf == 0) ? g : zn;
+                    }
+                }
+                // F's workspace store above is issued before this step's ring loads (the compiler
+                // must not hoist them): completing those loads then implies the store completed
+                wave_sync();
+                prefetch(PS, pk, u, std::integral_constant<bool, !ST>{});
+                step_barrier();
+            };
+            auto group = [&](auto SC, int kb, const Src& PS, int pkb) __attribute__((always_inline)) {
+                static_for<D>([&](auto UC) __attribute__((always_inline)) {
+                    step(UC, SC, kb, PS, pkb * D + decltype(UC)::value);
                 });
-                prefetch_next_group();
-            }
+            };
+            constexpr auto NS = std::integral_constant<bool, false>{};
+            constexpr auto SS = std::integral_constant<bool, true>{};
+            group(NS, 0, cur, 1);
+            int kb = 1;
+            for (; kb <= kb_steady && kb < G - 1; ++kb) group(SS, kb, cur, kb + 1);
+            for (; kb < G - 1; ++kb) group(NS, kb, cur, kb + 1);
+            group(NS, G - 1, nxt, 0);
+            cur = nxt;
+            nxt = src_of(i + 2);
         }
     };
     if (role == 0) run(std::integral_constant<int, 0>{});
