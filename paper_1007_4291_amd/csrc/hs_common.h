@@ -49,6 +49,11 @@ template <class T> __host__ __device__ __forceinline__ C2<T> cinv(C2<T> a) {
     return mk<T>(ar / d, -ai / d);
 }
 template <class T> __host__ __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+// c ? a : b component by component (a select of the whole vector struct can be lowered through
+// scratch memory)
+template <class T> __host__ __device__ __forceinline__ C2<T> csel(bool c, C2<T> a, C2<T> b) {
+    return mk<T>(c ? a.x : b.x, c ? a.y : b.y);
+}
 template <class To, class Ti> __host__ __device__ __forceinline__ C2<To> ccast(C2<Ti> a) {
     return mk<To>((To)a.x, (To)a.y);
 }

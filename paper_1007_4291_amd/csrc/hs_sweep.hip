@@ -197,7 +197,7 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
             const int k = kg + KS * jj;                   // k >= BS only in the last round of a k-split
             const CT l = ccast<T, TF>(cf[loff[jj]]);
             const CT xk = xv[q][KS == 1 ? jj : (k < BS ? k : 0)];
-            const CT t = (KS == 1 || k < BS) ? xk : mk<T>(0, 0);
+            const CT t = csel<T>(KS == 1 || k < BS, xk, mk<T>(0, 0));
             if (jj & 1) acc1 = cfma<T>(l, t, acc1);
             else acc0 = cfma<T>(l, t, acc0);
         }
@@ -265,13 +265,13 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
                 // backward pass of strip i-1, step s = n-1-k
                 CT ws = rsp[u];
 #pragma unroll
-                for (int j = 0; j < LAG; ++j) ws = (k == j + 1) ? wsnap[j] : ws;
+                for (int j = 0; j < LAG; ++j) ws = csel<T>(k == j + 1, wsnap[j], ws);
                 const CT xb = cfms<T>(colscalar(colb, XCOL_E), rowdot(colb, xbx), ws);
                 // forward pass of strip i: product for step k-1
                 const chunk16* cprev = colf[(u + 1) & 1];
                 const CT wf = rowdot(cprev, xfx);
                 // layer output of the backward pass
-                const CT x = k == 0 ? wcarry : xb;
+                const CT x = csel<T>(k == 0, wcarry, xb);
                 const CT yval = MODE == MODE_BWD ? csub<T>(ccast<T, double>(rb2[u]), x) : x;
                 gst((wy && bon) ? yrow + col - 1 : (HS_GLOBAL TO*)dummy, cvt_out<TO, T>(yval));
                 if (pb && bon) {
@@ -297,18 +297,18 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
                     if (MODE == MODE_FWD) {
                         double2 gv = ra[u];
                         if (!full_f) gv = csub<double>(gv, ccast<double, T>(cmul<T>(colscalar(cc, XCOL_APREV), ypart)));
-                        g = (full_f ? act : slot) ? ccast<T, double>(gv) : mk<T>(0, 0);
+                        g = csel<T>(full_f ? act : slot, ccast<T, double>(gv), mk<T>(0, 0));
                     } else if (MODE == MODE_BWD) {
-                        g = slot ? cmul<T>(colscalar(cc, XCOL_ANEXT), i == 0 ? ccast<T, double>(ra[u]) : ypart) : mk<T>(0, 0);
+                        g = csel<T>(slot, cmul<T>(colscalar(cc, XCOL_ANEXT), csel<T>(i == 0, ccast<T, double>(ra[u]), ypart)), mk<T>(0, 0));
                     } else if (MODE == MODE_MID) {
                         double2 gv = ra[u];
                         gv = csub<double>(gv, cmul<double>(ccast<double, T>(colscalar(cc, XCOL_APREV)), rb2[u]));
                         gv = csub<double>(gv, cmul<double>(ccast<double, T>(colscalar(cc, XCOL_ANEXT)), rc[u]));
-                        g = slot ? ccast<T, double>(gv) : mk<T>(0, 0);
+                        g = csel<T>(slot, ccast<T, double>(gv), mk<T>(0, 0));
                     } else {
-                        g = act ? ccast<T, double>(ra[u]) : mk<T>(0, 0);
+                        g = csel<T>(act, ccast<T, double>(ra[u]), mk<T>(0, 0));
                     }
-                    z = k == 0 ? g : cfms<T>(cmul<T>(colscalar(cprev, XCOL_E), is2f), w, g);
+                    z = csel<T>(k == 0, g, cfms<T>(cmul<T>(colscalar(cprev, XCOL_E), is2f), w, g));
                 }
                 prefetch(u, rbk[u], rfk[u], rsp[u], ra[u], rb2[u], rc[u]);
             });

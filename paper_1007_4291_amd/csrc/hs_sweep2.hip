@@ -253,16 +253,16 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
                         const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
                         colb[idx] = rk[u][c];
                     }
-                    xbx[q][r] = rok ? cmul<T>(is2b, xcur) : mk<T>(0, 0);   // padding rows read as zeros
+                    xbx[q][r] = csel<T>(rok, cmul<T>(is2b, xcur), mk<T>(0, 0));   // padding rows read as zeros
                     wave_sync();
                     CT ws = rsp[u];
                     if constexpr (!ST) {
                         // first group: w_{n-1-u} of strip i-1 from the ring of the previous pair
                         const CT wr = wring[(i + 1) & 1][(nmod - u + D) % D][lane];
-                        ws = kb == 0 ? wr : ws;
+                        ws = csel<T>(kb == 0, wr, ws);
                     }
                     const CT xb = cfms<T>(colscalar(colb, XCOL_E), rowdot(colb, xbx), ws);
-                    const CT x = (!ST && k == 0) ? ws : xb;
+                    const CT x = csel<T>(!ST && k == 0, ws, xb);
                     const CT yval = MODE == MODE_BWD ? csub<T>(ccast<T, double>(ra[u]), x) : x;
                     gst((ST ? wy : (wy && bon)) ? yrow + col - 1 : (HS_GLOBAL TO*)dummy, cvt_out<TO, T>(yval));
                     if (ST || bon) xcur = x;   // steady: unconditional (first pair: values unused)
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
                         const int idx = c * 64 + lane < N16 ? c * 64 + lane : N16 - 1;
                         colf[(u + 1) & 1][idx] = rk[u][c];
                     }
-                    xfx[q][r] = rok ? z : mk<T>(0, 0);
+                    xfx[q][r] = csel<T>(rok, z, mk<T>(0, 0));
                     wave_sync();
                     const chunk16* cc = colf[(u + 1) & 1];     // column kf
                     const chunk16* cprev = colf[u & 1];       // column kf - 1
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
                                      : mk<T>(0, 0);
                         }
                         const CT zn = cfms<T>(cmul<T>(colscalar(cprev, XCOL_E), is2f), w, g);
-                        z = (!ST && kf == 0) ? g : zn;
+                        z = csel<T>(!ST && kf == 0, g, zn);
                     }
                 }
                 // F's workspace store above is issued before this step's ring loads (the compiler
@@ -328,10 +328,13 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
     else run(std::integral_constant<int, 1>{});
 }
 
+// prefetch depth of the two-wave chains (each wave holds only its own strip's ring)
+template <class T, int BS> struct Ring2 { static constexpr int D = Ring<T, BS>::D; };
+
 template <class T, class TF, class TI, class TO, int BV, int MODE>
 static bool sweep2_bs(int ks, const ProbDev* probs, const ChainDev* chains, int nblocks, const IoDev* io, IoDev iov,
                       C2<T>* sp, hipStream_t s) {
-    constexpr int Q = RowsOf<BV>::Q, DV = Ring<T, BV>::D;
+    constexpr int Q = RowsOf<BV>::Q, DV = Ring2<T, BV>::D;
     dim3 g(nblocks), b(128);
     if (ks == 1) {
         hipLaunchKernelGGL((k_sweep2<T, TF, TI, TO, BV, MODE, DV, 1>), g, b, 0, s, probs, chains, io, iov, sp);
