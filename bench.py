@@ -191,6 +191,8 @@ def main():
           file=sys.stderr, flush=True)
 
     run = Runner(hs, torch, probs, prec)
+    schedule = run.batch.tune(reps=2)        # autotuned sweep schedule (setup, not timed)
+    print(f"[bench] schedule {schedule}", file=sys.stderr, flush=True)
     t_step, ph = timed(run, torch, a.steps, a.warmup)
     res = run.last
     print(f"[bench] {a.prec}: {t_step * 1e3:.1f} ms/step, iters {min(res.iters)}-{max(res.iters)}",
@@ -224,17 +226,19 @@ def main():
            "iters": {"min": min(res.iters), "max": max(res.iters), "mean": float(np.mean(res.iters))},
            "max_true_relres": max(res.relres),
            "phase_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in ph.items()},
+           "sweep_schedule": schedule,
            "roofline": roof}
 
     if a.fp64_steps > 0 and prec != hs.HELM_C128:
         del run
         torch.cuda.empty_cache()
         run64 = Runner(hs, torch, probs, hs.HELM_C128)
+        schedule64 = run64.batch.tune(reps=1)
         t64, _ = timed(run64, torch, a.fp64_steps, 1)
         err = max(float(torch.linalg.vector_norm(u1 - u2) / torch.linalg.vector_norm(u2))
                   for u1, u2 in zip(u_main, run64.u))
         out["fp64"] = {"value": tot_unknowns / t64, "ms_per_step": t64 * 1e3,
-                       "iters_max": max(run64.last.iters)}
+                       "iters_max": max(run64.last.iters), "sweep_schedule": schedule64}
         out["speedup_vs_fp64"] = t64 / t_step
         out["max_rel_err_vs_fp64_gpu"] = err
         print(f"[bench] c128: {t64 * 1e3:.1f} ms/step; speedup {t64 / t_step:.2f}x; err {err:.2e}",

@@ -135,7 +135,7 @@ struct sweep_factors_s {
     std::vector<int> sub_rows;
     // single-problem chain tables (rebuilt when nrhs changes)
     DevBuf chains, mids;
-    int chains_nrhs = -1, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1;
+    int chains_nrhs = -1, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1, waves = 1;
     helm_batch_t solo = nullptr;    // cached batch of one for fgmres_solve
     int solo_nrhs = -1, solo_restart = -1;
     ~sweep_factors_s();
@@ -147,7 +147,7 @@ struct helm_batch_s {
     std::vector<sweep_factors_t> M;
     std::vector<int> nrhs;
     std::vector<int64_t> N;
-    int nsys = 0, ntiles = 0, mv_blocks = 0, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1;
+    int nsys = 0, ntiles = 0, mv_blocks = 0, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1, waves = 1;
     std::vector<int> sys_prob, sys_rhs;
     std::vector<int32_t> tiles_h;
     DevBuf probs, chains, mids, io_sweep, io_apply, mv_z, mv_res, mv_blk, sv, tiles;
@@ -396,9 +396,9 @@ static bool two_wave_chains(int B) {
     const char* e = std::getenv("HELM_SWEEP_WAVES");
     return B <= 17 && !(e && std::atoi(e) == 1);
 }
-static bool run_chains(int B, int prec, int in_prec, int out_prec, int phase, int ks, const ProbDev* probs,
+static bool run_chains(int waves, int B, int prec, int in_prec, int out_prec, int phase, int ks, const ProbDev* probs,
                        const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
-    if (two_wave_chains(B))
+    if (waves == 2 && B <= 17)
         return launch_chains2(B, prec, in_prec, out_prec, phase, ks, probs, chains, nchains, io, io_val, spill, s);
     return launch_chains(B, prec, in_prec, out_prec, phase, ks, probs, chains, nchains, io, io_val, spill, s);
 }
@@ -423,6 +423,7 @@ static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
     const int n = A->n, B = A->B;
     int Q, Qm;
     rhs_grouping(B, nrhs, &Q, &M->ks_chain, &Qm, &M->ks_mid);
+    M->waves = two_wave_chains(B) ? 2 : 1;
     const int groups = (nrhs + Q - 1) / Q, mgroups = (nrhs + Qm - 1) / Qm;
     const int64_t per = chain_spill_elems(n);
     const size_t need = compute_elem(M->prec) * (size_t)per * (size_t)std::max(2 * groups, mgroups);
@@ -462,7 +463,7 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
     const int B = M->A->B;
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
-        if (!run_chains(B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
+        if (!run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
                            nullptr, io, M->spill.p, s))
             return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
         LAUNCHCHK();
@@ -475,7 +476,7 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
     }
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
-        run_chains(B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains, nullptr,
+        run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains, nullptr,
                       io, M->spill.p, s);
         LAUNCHCHK();
     }
@@ -509,6 +510,43 @@ extern "C" int sweep_subsolve(sweep_factors_t M, int32_t sub, const void* g, voi
 // ------------------------------------------------------------------------------------------------
 // a6 / a7: batched FGMRES
 // ------------------------------------------------------------------------------------------------
+// Chain and middle tables of a batch for a given k-split (right-hand sides per wave = row groups per
+// wave / k-split): problem-fronts in decreasing n, right-hand-side groups of each, and their
+// workspaces.  Reallocates the workspace only when it has to grow.
+static int build_chain_tables(helm_batch_t b, int ks, int ksm) {
+    const int B = b->B, count = b->count;
+    const int Q = chain_rhs_per_wave(B) / ks, Qm = middle_rhs_per_wave(B) / ksm;
+    std::vector<int> order(count);
+    for (int p = 0; p < count; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->A[a]->n > b->A[c]->n; });
+    std::vector<ChainDev> ch, md;
+    int64_t so = 0;
+    for (int p : order)
+        for (int g = 0; g * Q < b->nrhs[p]; ++g)
+            for (int f = 0; f < 2; ++f) {
+                ch.push_back(ChainDev{p, f, g * Q, std::min(Q, b->nrhs[p] - g * Q), so});
+                so += chain_spill_elems(b->A[p]->n);
+            }
+    int64_t mo = 0;
+    for (int p : order)
+        for (int g = 0; g * Qm < b->nrhs[p]; ++g) {
+            md.push_back(ChainDev{p, 0, g * Qm, std::min(Qm, b->nrhs[p] - g * Qm), mo});
+            mo += chain_spill_elems(b->A[p]->n);
+        }
+    int rc;
+    if ((rc = b->chains.alloc(sizeof(ChainDev) * ch.size()))) return rc;
+    if ((rc = b->mids.alloc(sizeof(ChainDev) * md.size()))) return rc;
+    HIPCHK(hipMemcpy(b->chains.p, ch.data(), sizeof(ChainDev) * ch.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->mids.p, md.data(), sizeof(ChainDev) * md.size(), hipMemcpyHostToDevice));
+    const size_t need = compute_elem(b->prec) * (size_t)std::max(so, mo);
+    if (b->spill.bytes < need && (rc = b->spill.alloc(need))) return rc;
+    b->nchains = (int)ch.size();
+    b->nmids = (int)md.size();
+    b->ks_chain = ks;
+    b->ks_mid = ksm;
+    return HELM_OK;
+}
+
 extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t* M, const int32_t* nrhs, int32_t count,
                                  int32_t restart, void* stream, helm_batch_t* out) {
     if (!A || !M || !nrhs || !out) return fail(HELM_EINVAL, "NULL argument");
@@ -582,32 +620,12 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
         HIPCHK(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
     }
     // chains (longest first), middles
-    int Q, Qm;
-    rhs_grouping(B, *std::max_element(b->nrhs.begin(), b->nrhs.end()), &Q, &b->ks_chain, &Qm, &b->ks_mid);
-    std::vector<int> order(count);
-    for (int p = 0; p < count; ++p) order[p] = p;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return A[a]->n > A[c]->n; });
-    std::vector<ChainDev> ch, md;
-    int64_t so = 0;
-    for (int p : order)
-        for (int g = 0; g * Q < b->nrhs[p]; ++g)
-            for (int f = 0; f < 2; ++f) {
-                ch.push_back(ChainDev{p, f, g * Q, std::min(Q, b->nrhs[p] - g * Q), so});
-                so += chain_spill_elems(A[p]->n);
-            }
-    int64_t mo = 0;
-    for (int p : order)
-        for (int g = 0; g * Qm < b->nrhs[p]; ++g) {
-            md.push_back(ChainDev{p, 0, g * Qm, std::min(Qm, b->nrhs[p] - g * Qm), mo});
-            mo += chain_spill_elems(A[p]->n);
-        }
-    b->nchains = (int)ch.size();
-    b->nmids = (int)md.size();
-    if ((rc = b->chains.alloc(sizeof(ChainDev) * ch.size()))) return rc;
-    if ((rc = b->mids.alloc(sizeof(ChainDev) * md.size()))) return rc;
-    HIPCHK(hipMemcpy(b->chains.p, ch.data(), sizeof(ChainDev) * ch.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(b->mids.p, md.data(), sizeof(ChainDev) * md.size(), hipMemcpyHostToDevice));
-    if ((rc = b->spill.alloc(compute_elem(b->prec) * (size_t)std::max(so, mo)))) return rc;
+    b->waves = two_wave_chains(B) ? 2 : 1;
+    {
+        int Q, Qm, ks, ksm;
+        rhs_grouping(B, *std::max_element(b->nrhs.begin(), b->nrhs.end()), &Q, &ks, &Qm, &ksm);
+        if ((rc = build_chain_tables(b.get(), ks, ksm))) return rc;
+    }
     // io tables for V_j -> Z_j, and matvec tables Z_j -> W
     std::vector<IoDev> ios((size_t)kk * count);
     std::vector<MvDev> mvz((size_t)kk * count);
@@ -729,7 +747,7 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, hipStream_
     const IoDev none{nullptr, nullptr, nullptr};
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
-        if (!run_chains(b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
+        if (!run_chains(b->waves, b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
                            b->spill.p, s))
             return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
         LAUNCHCHK();
@@ -741,10 +759,53 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, hipStream_
     }
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
-        run_chains(b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
+        run_chains(b->waves, b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
                       b->spill.p, s);
         LAUNCHCHK();
     }
+    return HELM_OK;
+}
+
+extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32_t* ksplit, int32_t* waves,
+                               double* ms) {
+    if (!b) return fail(HELM_EINVAL, "NULL argument");
+    if (reps < 1) reps = 1;
+    hipStream_t s = (hipStream_t)stream;
+    const int B = b->B, q = chain_rhs_per_wave(B);
+    const int ksm = b->ks_mid;
+    const int zprec = b->prec == HELM_C128 ? 0 : 1;
+    // input: the first Krylov block of every problem, zeroed (timing does not depend on the values)
+    for (int p = 0; p < b->count; ++p)
+        HIPCHK(hipMemsetAsync(b->V.as<double2>() + b->voff[p], 0, sizeof(double2) * b->nrhs[p] * b->N[p], s));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best_ks = b->ks_chain, best_w = b->waves, rc = HELM_OK;
+    double best = 1e300;
+    for (int w = (B <= 17 ? 2 : 1); w >= 1 && rc == HELM_OK; --w)
+        for (int ks = 1; ks <= q && rc == HELM_OK; ks *= 2) {
+            if (q % ks) continue;
+            if ((rc = build_chain_tables(b, ks, ksm))) break;
+            b->waves = w;
+            const IoDev* io = b->io_sweep.as<IoDev>();
+            if ((rc = batch_sweep(b, io, zprec, s))) break;   // warm-up
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(HELM_EHIP, "event record"); break; }
+            for (int r = 0; r < reps && rc == HELM_OK; ++r) rc = batch_sweep(b, io, zprec, s);
+            if (rc) break;
+            float t = 0.f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess) { rc = fail(HELM_EHIP, "event timing"); break; }
+            const double per = (double)t / reps;
+            if (per < best) { best = per; best_ks = ks; best_w = w; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = build_chain_tables(b, best_ks, ksm))) return rc;
+    b->waves = best_w;
+    if (ksplit) *ksplit = best_ks;
+    if (waves) *waves = best_w;
+    if (ms) *ms = best;
     return HELM_OK;
 }
 

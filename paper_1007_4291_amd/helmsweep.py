@@ -27,7 +27,7 @@ HELM_C64 = 1
 # every symbol the header declares
 EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_reassemble", "helm_problem_n", "helm_matvec",
            "sweep_factor", "sweep_refactor", "sweep_factor_bytes", "sweep_apply", "sweep_subsolve", "sweep_num_subproblems", "sweep_subproblem_rows",
-           "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "sweep_refactor_batch",
+           "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "sweep_refactor_batch", "helm_batch_tune",
            "helm_free", "sweep_free",
            "helm_batch_free", "helm_timing_enable", "helm_timing_read"]
 PHASES = ["assemble", "factor", "sweep_fwd", "sweep_mid", "sweep_bwd", "matvec", "krylov"]
@@ -68,6 +68,8 @@ def _load() -> C.CDLL:
         "fgmres_solve_batch": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), f64, i32, C.POINTER(i32), C.POINTER(f64), vp]),
         "sweep_apply_batch": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), vp]),
         "sweep_refactor_batch": (C.c_int, [vp, vp]),
+        "helm_batch_tune": (C.c_int, [vp, C.c_int32, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_double)]),
         "helm_free": (None, [vp]),
         "sweep_free": (None, [vp]),
         "helm_batch_free": (None, [vp]),
@@ -335,6 +337,15 @@ class Batch:
         rc = _lib.fgmres_solve_batch(self._h, fp, up, tol, maxit, it, rr, C.c_void_p(_stream(stream)))
         _check(rc, allow_notconv=True)
         return SolveResult(u, list(it), list(rr), rc == HELM_OK)
+
+    def tune(self, reps: int = 2, stream=None) -> dict:
+        """Pick the fastest sweep schedule for this batch by timing every candidate (a7 autotuner).
+
+        Overwrites the batch's Krylov work space.  Returns {"ksplit", "waves", "ms_per_apply"}."""
+        ks, wv, ms = C.c_int32(), C.c_int32(), C.c_double()
+        _check(_lib.helm_batch_tune(self._h, int(reps), C.c_void_p(_stream(stream)), C.byref(ks), C.byref(wv),
+                                    C.byref(ms)))
+        return {"ksplit": ks.value, "waves": wv.value, "ms_per_apply": ms.value}
 
     def refactor(self, stream=None):
         """Recompute the factors of every member in place (a2 over the whole batch, two launches)."""

@@ -336,3 +336,25 @@ def test_sweep_ksplit_parity(hs, torch, monkeypatch, ks, prec, waves):
     e2 = _rel(ub[1].cpu().numpy(), uo2)
     _log(f"  batch rel {e1:.2e} {e2:.2e}")
     assert e1 <= btol and e2 <= btol
+
+
+def test_batch_tune_keeps_results(hs, torch):
+    """The autotuner only changes the sweep schedule: after tuning, the batched application still
+    gives the oracle's M f, and the chosen schedule is one of the candidates."""
+    specs = [(47, 3), (63, 2), (39, 1)]
+    probs, facs, fs, mos = [], [], [], []
+    for n, R in specs:
+        op = OH.Params(n=n, omega=2 * math.pi * n / 8, alpha=2.0, pml_w=8, mpml_w=8)
+        c = workloads.velocity_layered(n, seed=n + 7)
+        A = _gpu_problem(hs, torch, op, c)
+        probs.append(A)
+        facs.append(hs.Factors(A, hs.HELM_C128))
+        fs.append(workloads.random_rhs(n, R, seed=n + 3))
+        mos.append(OS.factor(op, c))
+    b = hs.Batch(probs, facs, [R for _, R in specs], restart=4)
+    choice = b.tune(reps=1)
+    _log("tuned", choice)
+    assert choice["waves"] in (1, 2) and choice["ksplit"] in (1, 2, 4) and choice["ms_per_apply"] > 0
+    ub = b.apply([torch.as_tensor(f, device="cuda") for f in fs])
+    for u, f, Mo in zip(ub, fs, mos):
+        assert _rel(u.cpu().numpy(), OS.apply_sweep(Mo, f)) <= 1e-10
