@@ -397,10 +397,11 @@ static bool two_wave_chains(int B) {
     return B <= 17 && !(e && std::atoi(e) == 1);
 }
 static bool run_chains(int waves, int B, int prec, int in_prec, int out_prec, int phase, int ks, const ProbDev* probs,
-                       const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
+                       const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill,
+                       const int32_t* active, hipStream_t s) {
     if (waves == 2 && B <= 17)
-        return launch_chains2(B, prec, in_prec, out_prec, phase, ks, probs, chains, nchains, io, io_val, spill, s);
-    return launch_chains(B, prec, in_prec, out_prec, phase, ks, probs, chains, nchains, io, io_val, spill, s);
+        return launch_chains2(B, prec, in_prec, out_prec, phase, ks, probs, chains, nchains, io, io_val, spill, active, s);
+    return launch_chains(B, prec, in_prec, out_prec, phase, ks, probs, chains, nchains, io, io_val, spill, active, s);
 }
 
 static void rhs_grouping(int B, int max_nrhs, int* Q, int* ks, int* Qm, int* ksm) {
@@ -436,8 +437,9 @@ static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
     std::vector<ChainDev> ch, md;
     for (int g = 0; g < groups; ++g)
         for (int f = 0; f < 2; ++f)
-            ch.push_back(ChainDev{0, f, g * Q, std::min(Q, nrhs - g * Q), (int64_t)ch.size() * per});
-    for (int g = 0; g < mgroups; ++g) md.push_back(ChainDev{0, 0, g * Qm, std::min(Qm, nrhs - g * Qm), (int64_t)g * per});
+            ch.push_back(ChainDev{0, f, g * Q, std::min(Q, nrhs - g * Q), g * Q, 0, (int64_t)ch.size() * per});
+    for (int g = 0; g < mgroups; ++g)
+        md.push_back(ChainDev{0, 0, g * Qm, std::min(Qm, nrhs - g * Qm), g * Qm, 0, (int64_t)g * per});
     HIPCHK(hipStreamSynchronize(s));
     if ((rc = M->chains.alloc(sizeof(ChainDev) * ch.size()))) return rc;
     if ((rc = M->mids.alloc(sizeof(ChainDev) * md.size()))) return rc;
@@ -464,20 +466,20 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
         if (!run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
-                           nullptr, io, M->spill.p, s))
+                           nullptr, io, M->spill.p, nullptr, s))
             return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
         LAUNCHCHK();
     }
     {
         PhaseScope ph(PH_SWEEP_MID, s);
         launch_middle(B, M->prec, vec_prec, vec_prec, M->ks_mid, pd, M->mids.as<ChainDev>(), M->nmids, nullptr, io,
-                      M->spill.p, s);
+                      M->spill.p, nullptr, s);
         LAUNCHCHK();
     }
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
         run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains, nullptr,
-                      io, M->spill.p, s);
+                      io, M->spill.p, nullptr, s);
         LAUNCHCHK();
     }
     return HELM_OK;
@@ -519,18 +521,20 @@ static int build_chain_tables(helm_batch_t b, int ks, int ksm) {
     std::vector<int> order(count);
     for (int p = 0; p < count; ++p) order[p] = p;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->A[a]->n > b->A[c]->n; });
+    std::vector<int> base(count + 1, 0);      // first system index of each problem
+    for (int p = 0; p < count; ++p) base[p + 1] = base[p] + b->nrhs[p];
     std::vector<ChainDev> ch, md;
     int64_t so = 0;
     for (int p : order)
         for (int g = 0; g * Q < b->nrhs[p]; ++g)
             for (int f = 0; f < 2; ++f) {
-                ch.push_back(ChainDev{p, f, g * Q, std::min(Q, b->nrhs[p] - g * Q), so});
+                ch.push_back(ChainDev{p, f, g * Q, std::min(Q, b->nrhs[p] - g * Q), base[p] + g * Q, 0, so});
                 so += chain_spill_elems(b->A[p]->n);
             }
     int64_t mo = 0;
     for (int p : order)
         for (int g = 0; g * Qm < b->nrhs[p]; ++g) {
-            md.push_back(ChainDev{p, 0, g * Qm, std::min(Qm, b->nrhs[p] - g * Qm), mo});
+            md.push_back(ChainDev{p, 0, g * Qm, std::min(Qm, b->nrhs[p] - g * Qm), base[p] + g * Qm, 0, mo});
             mo += chain_spill_elems(b->A[p]->n);
         }
     int rc;
@@ -741,26 +745,28 @@ extern "C" int helm_timing_read(double* ms, int64_t* launches, int32_t reset) {
 }
 
 // Enqueue M_alpha on the batch: io table `io` (device, one entry per problem), in complex128,
-// out complex128 or complex64 (the factor precision for FGMRES directions).
-static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, hipStream_t s) {
+// out complex128 or complex64 (the factor precision for FGMRES directions).  active: per-system
+// device flags (nullptr: all); chains and middles whose systems are all inactive are skipped.
+static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int32_t* active, hipStream_t s) {
     const ProbDev* pd = b->probs.as<ProbDev>();
     const IoDev none{nullptr, nullptr, nullptr};
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
         if (!run_chains(b->waves, b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
-                           b->spill.p, s))
+                           b->spill.p, active, s))
             return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
         LAUNCHCHK();
     }
     {
         PhaseScope ph(PH_SWEEP_MID, s);
-        launch_middle(b->B, b->prec, 0, out_prec, b->ks_mid, pd, b->mids.as<ChainDev>(), b->nmids, io, none, b->spill.p, s);
+        launch_middle(b->B, b->prec, 0, out_prec, b->ks_mid, pd, b->mids.as<ChainDev>(), b->nmids, io, none, b->spill.p,
+                      active, s);
         LAUNCHCHK();
     }
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
         run_chains(b->waves, b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
-                      b->spill.p, s);
+                      b->spill.p, active, s);
         LAUNCHCHK();
     }
     return HELM_OK;
@@ -788,9 +794,9 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
             if ((rc = build_chain_tables(b, ks, ksm))) break;
             b->waves = w;
             const IoDev* io = b->io_sweep.as<IoDev>();
-            if ((rc = batch_sweep(b, io, zprec, s))) break;   // warm-up
+            if ((rc = batch_sweep(b, io, zprec, nullptr, s))) break;   // warm-up
             if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(HELM_EHIP, "event record"); break; }
-            for (int r = 0; r < reps && rc == HELM_OK; ++r) rc = batch_sweep(b, io, zprec, s);
+            for (int r = 0; r < reps && rc == HELM_OK; ++r) rc = batch_sweep(b, io, zprec, nullptr, s);
             if (rc) break;
             float t = 0.f;
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -819,7 +825,7 @@ extern "C" int sweep_apply_batch(helm_batch_t b, const void* const* f, void* con
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemcpy(b->io_apply.p, io.data(), sizeof(IoDev) * b->count, hipMemcpyHostToDevice));
-    return batch_sweep(b, b->io_apply.as<IoDev>(), 0, s);
+    return batch_sweep(b, b->io_apply.as<IoDev>(), 0, nullptr, s);
 }
 
 extern "C" int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* const* u, double tol, int32_t maxit,
@@ -899,7 +905,7 @@ extern "C" int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* co
         launch_scale_to_v(dsv, dt, ns, nt, 0, b->inv.as<double>(), b->active.as<int32_t>(), s);
         LAUNCHCHK();
         for (int j = 0; j < kk; ++j) {
-            int rc = batch_sweep(b, b->io_sweep.as<IoDev>() + (size_t)j * b->count, zprec, s);
+            int rc = batch_sweep(b, b->io_sweep.as<IoDev>() + (size_t)j * b->count, zprec, b->active.as<int32_t>(), s);
             if (rc) return rc;
             {
                 PhaseScope ph(PH_MATVEC, s);

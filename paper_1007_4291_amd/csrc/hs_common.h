@@ -139,8 +139,17 @@ struct ChainDev {
     int32_t prob;
     int32_t front;      // 0: upward front (F, B+1, ..., c-1); 1: downward front (E, n-B, ..., c+1)
     int32_t rhs0, nq;   // first right-hand side and count (<= lanes / padded rows)
+    int32_t sys0;       // system index of the first right-hand side (batch order, problem-major)
+    int32_t pad_;
     int64_t spill_off;  // offset of this chain's workspace (complex elements)
 };
+
+// True if one of the chain's systems is still active (the result is the same in every lane).
+__device__ inline bool any_active(const int32_t* active, const ChainDev& ch) {
+    int a = 0;
+    for (int i = 0; i < ch.nq; ++i) a |= active[ch.sys0 + i];
+    return a != 0;
+}
 
 // Per-problem vector pointers for one application of the sweep (or one matvec).
 struct IoDev {

@@ -57,14 +57,19 @@ bool launch_factor(int bs, int prec, const ProbDev* probs, const SubDev* subs, i
 // io: device table indexed by ChainDev::prob, or nullptr to use io_val for every chain.
 // ksplit: 1 (each 16/32/64-lane row group serves its own right-hand side) or the number of row
 // groups per wave (all groups serve one right-hand side, splitting each block-vector product).
+// active: per-system flags indexed by ChainDev::sys0 + i (i < nq), or nullptr; a chain whose
+// systems are all inactive does nothing (its outputs keep their previous contents).
 bool launch_chains(int B, int prec, int in_prec, int out_prec, int phase, int ksplit, const ProbDev* probs,
-                   const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s);
+                   const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill,
+                   const int32_t* active, hipStream_t s);
 // The same chains with two waves per chain (backward and forward pass on separate waves, one LDS
 // barrier per step); strip heights up to 17.
 bool launch_chains2(int B, int prec, int in_prec, int out_prec, int phase, int ksplit, const ProbDev* probs,
-                    const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s);
+                    const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill,
+                    const int32_t* active, hipStream_t s);
 bool launch_middle(int B, int prec, int in_prec, int out_prec, int ksplit, const ProbDev* probs,
-                   const ChainDev* mids, int nmids, const IoDev* io, IoDev io_val, void* spill, hipStream_t s);
+                   const ChainDev* mids, int nmids, const IoDev* io, IoDev io_val, void* spill,
+                   const int32_t* active, hipStream_t s);
 // Lanes per row group (right-hand sides per wave) for chains of strip height B and for the middle.
 int chain_rhs_per_wave(int B);
 int middle_rhs_per_wave(int B);

@@ -19,7 +19,7 @@ namespace hs {
 template <class T, class TF, class TI, class TO, int BS, int MODE, int D, int KS>
 __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
                                               const IoDev* __restrict__ io, IoDev io_val, C2<T>* __restrict__ spill_base,
-                                              SubArg sa) {
+                                              const int32_t* __restrict__ active, SubArg sa) {
     using CT = C2<T>;
     using CF = C2<TF>;
     constexpr int RP = RowsOf<BS>::RP, Q = RowsOf<BS>::Q;
@@ -39,8 +39,11 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
     const int lane = threadIdx.x, r = lane % RP, q = lane / RP;
     const int rq = q / KS, kg = q % KS;
     constexpr int KMAX = (BS + KS - 1) / KS;
-    ChainDev ch{0, 0, 0, 0, 0};
-    if (MODE != MODE_SUB) ch = chains[blockIdx.x];
+    ChainDev ch{0, 0, 0, 0, 0, 0, 0};
+    if (MODE != MODE_SUB) {
+        ch = chains[blockIdx.x];
+        if (active && !any_active(active, ch)) return;   // every right-hand side of the chain is frozen
+    }
     const ProbDev& P = probs[ch.prob];
     const IoDev IO = io ? io[ch.prob] : io_val;
     // problem scalars, loaded once
@@ -323,22 +326,22 @@ __global__ __launch_bounds__(64) void k_sweep(const ProbDev* __restrict__ probs,
 
 template <class T, class TF, class TI, class TO, int BV, int MODE>
 static bool sweep_bs(int ks, const ProbDev* probs, const ChainDev* chains, int nblocks, const IoDev* io, IoDev iov,
-                     C2<T>* sp, const SubArg& sa, hipStream_t s) {
+                     C2<T>* sp, const int32_t* act, const SubArg& sa, hipStream_t s) {
     constexpr int Q = RowsOf<BV>::Q, DV = Ring<T, BV>::D;
     dim3 g(nblocks), b(64);
     if (ks == 1) {
-        hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, DV, 1>), g, b, 0, s, probs, chains, io, iov, sp, sa);
+        hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, DV, 1>), g, b, 0, s, probs, chains, io, iov, sp, act, sa);
         return true;
     }
     if constexpr (Q >= 4) {
         if (ks == 2) {
-            hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, DV, 2>), g, b, 0, s, probs, chains, io, iov, sp, sa);
+            hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, DV, 2>), g, b, 0, s, probs, chains, io, iov, sp, act, sa);
             return true;
         }
     }
     if constexpr (Q >= 2) {
         if (ks == Q) {
-            hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, DV, Q>), g, b, 0, s, probs, chains, io, iov, sp, sa);
+            hipLaunchKernelGGL((k_sweep<T, TF, TI, TO, BV, MODE, DV, Q>), g, b, 0, s, probs, chains, io, iov, sp, act, sa);
             return true;
         }
     }
@@ -347,11 +350,11 @@ static bool sweep_bs(int ks, const ProbDev* probs, const ChainDev* chains, int n
 
 template <class T, class TF, class TI, class TO, int MODE>
 static bool sweep_typed(int bs, int ks, const ProbDev* probs, const ChainDev* chains, int nblocks, const IoDev* io,
-                        IoDev iov, void* spill, const SubArg& sa, hipStream_t s) {
+                        IoDev iov, void* spill, const int32_t* act, const SubArg& sa, hipStream_t s) {
     C2<T>* sp = (C2<T>*)spill;
     switch (bs) {
 #define HS_CASE(BV) \
-    case BV: return sweep_bs<T, TF, TI, TO, BV, MODE>(ks, probs, chains, nblocks, io, iov, sp, sa, s);
+    case BV: return sweep_bs<T, TF, TI, TO, BV, MODE>(ks, probs, chains, nblocks, io, iov, sp, act, sa, s);
         HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13) HS_CASE(17) HS_CASE(25) HS_CASE(33)
 #undef HS_CASE
         default: return false;
@@ -360,35 +363,39 @@ static bool sweep_typed(int bs, int ks, const ProbDev* probs, const ChainDev* ch
 
 template <int MODE>
 static bool sweep_prec(int bs, int ks, int prec, int in_prec, int out_prec, const ProbDev* probs, const ChainDev* chains,
-                       int nb, const IoDev* io, IoDev iov, void* spill, const SubArg& sa, hipStream_t s) {
+                       int nb, const IoDev* io, IoDev iov, void* spill, const int32_t* act, const SubArg& sa,
+                       hipStream_t s) {
     if (prec == 0) {
         if (in_prec == 0 && out_prec == 0)
-            return sweep_typed<double, double, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, sa, s);
+            return sweep_typed<double, double, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, act, sa, s);
         return false;
     }
     if (in_prec == 0 && out_prec == 0)
-        return sweep_typed<float, float, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, sa, s);
+        return sweep_typed<float, float, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, act, sa, s);
     if (in_prec == 0 && out_prec == 1)
-        return sweep_typed<float, float, double2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, sa, s);
+        return sweep_typed<float, float, double2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, act, sa, s);
     if (in_prec == 1 && out_prec == 1)
-        return sweep_typed<float, float, float2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, sa, s);
+        return sweep_typed<float, float, float2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, act, sa, s);
     return false;
 }
 
 bool launch_chains(int B, int prec, int in_prec, int out_prec, int phase, int ksplit, const ProbDev* probs,
-                   const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
+                   const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill,
+                   const int32_t* active, hipStream_t s) {
     if (nchains <= 0) return true;
     SubArg sa{};
-    return phase == 0
-               ? sweep_prec<MODE_FWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, spill, sa, s)
-               : sweep_prec<MODE_BWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, spill, sa, s);
+    return phase == 0 ? sweep_prec<MODE_FWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val,
+                                             spill, active, sa, s)
+                      : sweep_prec<MODE_BWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val,
+                                             spill, active, sa, s);
 }
 
 bool launch_middle(int B, int prec, int in_prec, int out_prec, int ksplit, const ProbDev* probs, const ChainDev* mids,
-                   int nmids, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
+                   int nmids, const IoDev* io, IoDev io_val, void* spill, const int32_t* active, hipStream_t s) {
     if (nmids <= 0) return true;
     SubArg sa{};
-    return sweep_prec<MODE_MID>(2 * B - 1, ksplit, prec, in_prec, out_prec, probs, mids, nmids, io, io_val, spill, sa, s);
+    return sweep_prec<MODE_MID>(2 * B - 1, ksplit, prec, in_prec, out_prec, probs, mids, nmids, io, io_val, spill,
+                                active, sa, s);
 }
 
 int chain_padded_rows(int B) { return B <= 16 ? 16 : (B <= 32 ? 32 : 64); }
@@ -401,8 +408,8 @@ bool launch_subsolve(int bs, int prec, const ProbDev* prob, const void* fac, con
     SubArg sa{fac, (const double2*)g, (double2*)x, ris2, nrhs, rstep, cdir, jl};
     IoDev none{nullptr, nullptr, nullptr};
     const int nb = (nrhs + Q - 1) / Q;
-    if (prec == 0) return sweep_typed<double, double, double2, double2, MODE_SUB>(bs, 1, prob, nullptr, nb, nullptr, none, spill, sa, s);
-    return sweep_typed<float, float, double2, double2, MODE_SUB>(bs, 1, prob, nullptr, nb, nullptr, none, spill, sa, s);
+    if (prec == 0) return sweep_typed<double, double, double2, double2, MODE_SUB>(bs, 1, prob, nullptr, nb, nullptr, none, spill, nullptr, sa, s);
+    return sweep_typed<float, float, double2, double2, MODE_SUB>(bs, 1, prob, nullptr, nb, nullptr, none, spill, nullptr, sa, s);
 }
 
 }  // namespace hs

@@ -31,7 +31,8 @@ __device__ __forceinline__ void step_barrier() {
 
 template <class T, class TF, class TI, class TO, int BS, int MODE, int D, int KS>
 __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
-                                               const IoDev* __restrict__ io, IoDev io_val, C2<T>* __restrict__ spill_base) {
+                                               const IoDev* __restrict__ io, IoDev io_val, C2<T>* __restrict__ spill_base,
+                                               const int32_t* __restrict__ active) {
     static_assert(MODE == MODE_FWD || MODE == MODE_BWD, "two-wave chains serve the front phases");
     static_assert(D % 2 == 0, "slot parities must be compile-time values");
     using CT = C2<T>;
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(128) void k_sweep2(const ProbDev* __restrict__ prob
     constexpr int KMAX = (BS + KS - 1) / KS;
     static_assert(BS + KS - 1 <= RP, "the k-split's last round must stay inside the padded rows");
     const ChainDev ch = chains[blockIdx.x];
+    if (active && !any_active(active, ch)) return;   // both waves leave before the first barrier
     const ProbDev& P = probs[ch.prob];
     const IoDev IO = io ? io[ch.prob] : io_val;
     const int n = P.n, B = P.B, cmid = P.c;
@@ -333,22 +335,22 @@ template <class T, int BS> struct Ring2 { static constexpr int D = Ring<T, BS>::
 
 template <class T, class TF, class TI, class TO, int BV, int MODE>
 static bool sweep2_bs(int ks, const ProbDev* probs, const ChainDev* chains, int nblocks, const IoDev* io, IoDev iov,
-                      C2<T>* sp, hipStream_t s) {
+                      C2<T>* sp, const int32_t* act, hipStream_t s) {
     constexpr int Q = RowsOf<BV>::Q, DV = Ring2<T, BV>::D;
     dim3 g(nblocks), b(128);
     if (ks == 1) {
-        hipLaunchKernelGGL((k_sweep2<T, TF, TI, TO, BV, MODE, DV, 1>), g, b, 0, s, probs, chains, io, iov, sp);
+        hipLaunchKernelGGL((k_sweep2<T, TF, TI, TO, BV, MODE, DV, 1>), g, b, 0, s, probs, chains, io, iov, sp, act);
         return true;
     }
     if constexpr (Q >= 4) {
         if (ks == 2) {
-            hipLaunchKernelGGL((k_sweep2<T, TF, TI, TO, BV, MODE, DV, 2>), g, b, 0, s, probs, chains, io, iov, sp);
+            hipLaunchKernelGGL((k_sweep2<T, TF, TI, TO, BV, MODE, DV, 2>), g, b, 0, s, probs, chains, io, iov, sp, act);
             return true;
         }
     }
     if constexpr (Q >= 2) {
         if (ks == Q) {
-            hipLaunchKernelGGL((k_sweep2<T, TF, TI, TO, BV, MODE, DV, Q>), g, b, 0, s, probs, chains, io, iov, sp);
+            hipLaunchKernelGGL((k_sweep2<T, TF, TI, TO, BV, MODE, DV, Q>), g, b, 0, s, probs, chains, io, iov, sp, act);
             return true;
         }
     }
@@ -357,11 +359,11 @@ static bool sweep2_bs(int ks, const ProbDev* probs, const ChainDev* chains, int 
 
 template <class T, class TF, class TI, class TO, int MODE>
 static bool sweep2_typed(int bs, int ks, const ProbDev* probs, const ChainDev* chains, int nblocks, const IoDev* io,
-                         IoDev iov, void* spill, hipStream_t s) {
+                         IoDev iov, void* spill, const int32_t* act, hipStream_t s) {
     C2<T>* sp = (C2<T>*)spill;
     switch (bs) {
 #define HS_CASE(BV) \
-    case BV: return sweep2_bs<T, TF, TI, TO, BV, MODE>(ks, probs, chains, nblocks, io, iov, sp, s);
+    case BV: return sweep2_bs<T, TF, TI, TO, BV, MODE>(ks, probs, chains, nblocks, io, iov, sp, act, s);
         HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13) HS_CASE(17)
 #undef HS_CASE
         default: return false;
@@ -370,26 +372,30 @@ static bool sweep2_typed(int bs, int ks, const ProbDev* probs, const ChainDev* c
 
 template <int MODE>
 static bool sweep2_prec(int bs, int ks, int prec, int in_prec, int out_prec, const ProbDev* probs,
-                        const ChainDev* chains, int nb, const IoDev* io, IoDev iov, void* spill, hipStream_t s) {
+                        const ChainDev* chains, int nb, const IoDev* io, IoDev iov, void* spill, const int32_t* act,
+                        hipStream_t s) {
     if (prec == 0) {
         if (in_prec == 0 && out_prec == 0)
-            return sweep2_typed<double, double, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, s);
+            return sweep2_typed<double, double, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, act, s);
         return false;
     }
     if (in_prec == 0 && out_prec == 0)
-        return sweep2_typed<float, float, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, s);
+        return sweep2_typed<float, float, double2, double2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, act, s);
     if (in_prec == 0 && out_prec == 1)
-        return sweep2_typed<float, float, double2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, s);
+        return sweep2_typed<float, float, double2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, act, s);
     if (in_prec == 1 && out_prec == 1)
-        return sweep2_typed<float, float, float2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, s);
+        return sweep2_typed<float, float, float2, float2, MODE>(bs, ks, probs, chains, nb, io, iov, spill, act, s);
     return false;
 }
 
 bool launch_chains2(int B, int prec, int in_prec, int out_prec, int phase, int ksplit, const ProbDev* probs,
-                    const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill, hipStream_t s) {
+                    const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill,
+                    const int32_t* active, hipStream_t s) {
     if (nchains <= 0) return true;
-    return phase == 0 ? sweep2_prec<MODE_FWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, spill, s)
-                      : sweep2_prec<MODE_BWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, spill, s);
+    return phase == 0 ? sweep2_prec<MODE_FWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val,
+                                              spill, active, s)
+                      : sweep2_prec<MODE_BWD>(B, ksplit, prec, in_prec, out_prec, probs, chains, nchains, io, io_val,
+                                              spill, active, s);
 }
 
 }  // namespace hs
