@@ -156,15 +156,20 @@ int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* const* u, dou
 int sweep_apply_batch(helm_batch_t b, const void* const* f, void* const* u, void* stream);
 
 /* a7 -- Autotune the batch's sweep schedule: times the batched preconditioner application (on the
- * batch's own first Krylov block, zeroed) for every candidate schedule -- waves per chain (two: the
- * backward and forward pass of a strip pair on separate waves, for strip heights <= 17; one) and
- * the number of row groups each right-hand side's block products are split over (1, 2, 4, ...
- * dividing the row groups of a wave) -- `reps` times each after one warm-up, and keeps the fastest
- * for all later solves and applications of the batch.  Results are unchanged up to rounding order.
- *   ksplit, waves: host (may be NULL): the chosen split and waves per chain
+ * batch's own first Krylov block, zeroed) for every candidate schedule and keeps the fastest for all
+ * later solves and applications of the batch.  Candidates: the segmented chains (every strip solve
+ * split into 16-column segments joined by a short sequential pass over segment propagators; strip
+ * heights <= 16 and n <= 1024, or 832 for complex128 factors), and the plain chains with two waves
+ * per chain (backward and forward pass of a strip pair on separate waves, heights <= 17) or one,
+ * each with the number of row groups every right-hand side's block products are split over (1, 2,
+ * 4, ... dividing the row groups of a wave).  Each is run `reps` times after one warm-up.  Results
+ * are unchanged up to rounding order.
+ *   ksplit, waves, segmented: host (may be NULL): the chosen plain-chain split and waves per chain,
+ *                             and 1 if the segmented chains won (then ksplit / waves are unused)
  *   ms: host (may be NULL): its time per application, milliseconds
  * Overwrites the batch's Krylov work space; synchronises `stream`. */
-int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32_t* ksplit, int32_t* waves, double* ms);
+int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32_t* ksplit, int32_t* waves,
+                    int32_t* segmented, double* ms);
 
 /* a2 for the whole batch (Algorithm 3 for every problem): recompute the factors of every member
  * from its problem's current tables, all height-B strips of all problems in one launch and the

@@ -131,11 +131,16 @@ struct sweep_factors_s {
     int prec = 0;
     DevBuf fac, subs, spill, status;
     int64_t fac_elems = 0;
+    // segmented sweep: propagators of the front strips and their work table (seg: available)
+    DevBuf prop, propw;
+    int npropw = 0;
+    bool seg = false;
     std::vector<SubDev> hsubs;
     std::vector<int> sub_rows;
     // single-problem chain tables (rebuilt when nrhs changes)
-    DevBuf chains, mids;
+    DevBuf chains, mids, segch;
     int chains_nrhs = -1, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1, waves = 1;
+    int nsegch = 0, seg_wg = 0, kind = 0;   // kind 1: segmented chains
     helm_batch_t solo = nullptr;    // cached batch of one for fgmres_solve
     int solo_nrhs = -1, solo_restart = -1;
     ~sweep_factors_s();
@@ -159,6 +164,10 @@ struct helm_batch_s {
     // second stream so that the two launches overlap
     DevBuf fsubs, msubs, fstatus;
     int nfsubs = 0, nmsubs = 0;
+    // segmented sweep: propagator work of all problems, chain table, workgroup waves; kind 1 selects it
+    DevBuf propw, segch;
+    int npropw = 0, nsegch = 0, seg_wg = 0, kind = 0;
+    bool seg = false;
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     ~helm_batch_s() {
@@ -281,6 +290,17 @@ extern "C" int helm_matvec(helm_problem_t A, const void* x, int32_t x_prec, void
 // ------------------------------------------------------------------------------------------------
 // a2: factorisation
 // ------------------------------------------------------------------------------------------------
+// Segmented sweep sizes: segments per strip, waves per right-hand side (4 segments per wave).
+static int seg_count(int n) { return (n + SEG - 1) / SEG; }
+static int seg_waves_rhs(int n) { return (seg_count(n) + 3) / 4; }
+// Propagator pair (column- and row-major RP x RP blocks) per segment, complex elements.
+constexpr int64_t kSegPH = 2 * 16 * 16;
+// HELM_SWEEP_SEG=0 / 1 forces the plain / segmented chains; unset: segmented where available.
+static int seg_env() {
+    const char* e = std::getenv("HELM_SWEEP_SEG");
+    return e ? std::atoi(e) : -1;
+}
+
 // Run the a2 kernels for every strip of M's problem and check the pivots.
 static int factor_into(sweep_factors_t M, hipStream_t s) {
     helm_problem_t A = M->A;
@@ -296,6 +316,11 @@ static int factor_into(sweep_factors_t M, hipStream_t s) {
         if (!launch_factor(2 * B - 1, M->prec, pd, M->subs.as<SubDev>() + (A->nsub - 1), 1, M->status.as<int>(), s))
             return fail(HELM_EINVAL, "no factor kernel for middle height %d", 2 * B - 1);
         LAUNCHCHK();
+        if (M->seg) {
+            if (!launch_prop(B, M->prec, pd, M->propw.as<PropDev>(), M->npropw, s))
+                return fail(HELM_EINVAL, "no propagator kernel for B=%d", B);
+            LAUNCHCHK();
+        }
     }
     int st = 0;
     HIPCHK(hipMemcpyAsync(&st, M->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -359,6 +384,21 @@ extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_
     if ((rc = M->subs.alloc(sizeof(SubDev) * S.size()))) return rc;
     if ((rc = M->status.alloc(sizeof(int)))) return rc;
     HIPCHK(hipMemcpy(M->subs.p, S.data(), sizeof(SubDev) * S.size(), hipMemcpyHostToDevice));
+    // segmented sweep: propagators of every segment of every front strip (not the middle)
+    M->seg = seg_supported(B) && seg_waves_rhs(n) <= seg_max_waves(prec == HELM_C128 ? 0 : 1, B);
+    if (M->seg) {
+        const int Sg = seg_count(n);
+        const int64_t per_strip = (int64_t)Sg * kSegPH;
+        if ((rc = M->prop.alloc(esz * (size_t)per_strip * (size_t)(A->nsub - 1)))) return rc;
+        std::vector<PropDev> pw;
+        for (int u = 0; u + 1 < A->nsub; ++u)
+            for (int g = 0; g * 4 < Sg; ++g)
+                pw.push_back(PropDev{0, S[u].cdir, S[u].rstep, g * 4, S[u].facp, S[u].ris2,
+                                     (char*)M->prop.p + esz * (size_t)(u * per_strip)});
+        if ((rc = M->propw.alloc(sizeof(PropDev) * pw.size()))) return rc;
+        HIPCHK(hipMemcpy(M->propw.p, pw.data(), sizeof(PropDev) * pw.size(), hipMemcpyHostToDevice));
+        M->npropw = (int)pw.size();
+    }
     if ((rc = factor_into(M.get(), s))) return rc;
     *out = M.release();
     return HELM_OK;
@@ -418,6 +458,26 @@ static void rhs_grouping(int B, int max_nrhs, int* Q, int* ks, int* Qm, int* ksm
     *Qm = qm / *ksm;
 }
 
+// Segmented chain table: every workgroup has wg waves; problem p (largest first) gives each
+// right-hand side seg_waves_rhs(n_p) of them, wg / that right-hand sides per workgroup and front.
+static std::vector<ChainDev> seg_table(const std::vector<int>& n, const std::vector<int>& nrhs, int* wg) {
+    const int count = (int)n.size();
+    int w = 1;
+    for (int p = 0; p < count; ++p) w = std::max(w, seg_waves_rhs(n[p]));
+    std::vector<int> order(count), base(count + 1, 0);
+    for (int p = 0; p < count; ++p) { order[p] = p; base[p + 1] = base[p] + nrhs[p]; }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n[a] > n[c]; });
+    std::vector<ChainDev> ch;
+    for (int p : order) {
+        const int wr = seg_waves_rhs(n[p]), R = std::max(1, w / wr);
+        for (int g = 0; g * R < nrhs[p]; ++g)
+            for (int f = 0; f < 2; ++f)
+                ch.push_back(ChainDev{p, f, g * R, std::min(R, nrhs[p] - g * R), base[p] + g * R, wr, 0});
+    }
+    *wg = w;
+    return ch;
+}
+
 // Single-problem chain tables: groups of Q right-hand sides per front, Qm per middle wave.
 static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
     helm_problem_t A = M->A;
@@ -447,6 +507,14 @@ static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
     HIPCHK(hipMemcpy(M->mids.p, md.data(), sizeof(ChainDev) * md.size(), hipMemcpyHostToDevice));
     M->nchains = (int)ch.size();
     M->nmids = (int)md.size();
+    M->kind = 0;
+    if (M->seg) {
+        const std::vector<ChainDev> sc = seg_table({n}, {nrhs}, &M->seg_wg);
+        if ((rc = M->segch.alloc(sizeof(ChainDev) * sc.size()))) return rc;
+        HIPCHK(hipMemcpy(M->segch.p, sc.data(), sizeof(ChainDev) * sc.size(), hipMemcpyHostToDevice));
+        M->nsegch = (int)sc.size();
+        M->kind = seg_env() == 0 ? 0 : 1;
+    }
     M->chains_nrhs = nrhs;
     return HELM_OK;
 }
@@ -461,13 +529,16 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
     int rc = ensure_solo_chains(M, nrhs, s);
     if (rc) return rc;
     const ProbDev* pd = M->A->pd.as<ProbDev>();
-    IoDev io{f, u, M->fac.p};
+    IoDev io{f, u, M->fac.p, M->prop.p};
     const int B = M->A->B;
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
-        if (!run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
-                           nullptr, io, M->spill.p, nullptr, s))
-            return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
+        const bool ok = M->kind == 1
+                            ? launch_chains_seg(B, M->prec, vec_prec, vec_prec, 0, pd, M->segch.as<ChainDev>(), M->nsegch,
+                                                nullptr, io, M->seg_wg, nullptr, s)
+                            : run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd,
+                                         M->chains.as<ChainDev>(), M->nchains, nullptr, io, M->spill.p, nullptr, s);
+        if (!ok) return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
         LAUNCHCHK();
     }
     {
@@ -478,8 +549,12 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
     }
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
-        run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains, nullptr,
-                      io, M->spill.p, nullptr, s);
+        if (M->kind == 1)
+            launch_chains_seg(B, M->prec, vec_prec, vec_prec, 1, pd, M->segch.as<ChainDev>(), M->nsegch, nullptr, io,
+                              M->seg_wg, nullptr, s);
+        else
+            run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
+                       nullptr, io, M->spill.p, nullptr, s);
         LAUNCHCHK();
     }
     return HELM_OK;
@@ -630,6 +705,30 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
         rhs_grouping(B, *std::max_element(b->nrhs.begin(), b->nrhs.end()), &Q, &ks, &Qm, &ksm);
         if ((rc = build_chain_tables(b.get(), ks, ksm))) return rc;
     }
+    // segmented chains and the propagator work of all problems
+    b->seg = true;
+    for (int p = 0; p < count; ++p) b->seg = b->seg && M[p]->seg;
+    if (b->seg) {
+        std::vector<int> nv(count);
+        for (int p = 0; p < count; ++p) nv[p] = A[p]->n;
+        const std::vector<ChainDev> sc = seg_table(nv, b->nrhs, &b->seg_wg);
+        if (b->seg_wg > seg_max_waves(b->prec == HELM_C128 ? 0 : 1, B)) b->seg = false;
+        if (b->seg) {
+            if ((rc = b->segch.alloc(sizeof(ChainDev) * sc.size()))) return rc;
+            HIPCHK(hipMemcpy(b->segch.p, sc.data(), sizeof(ChainDev) * sc.size(), hipMemcpyHostToDevice));
+            b->nsegch = (int)sc.size();
+            std::vector<PropDev> pw;
+            for (int p = 0; p < count; ++p) {
+                std::vector<PropDev> one(M[p]->npropw);
+                HIPCHK(hipMemcpy(one.data(), M[p]->propw.p, sizeof(PropDev) * one.size(), hipMemcpyDeviceToHost));
+                for (PropDev& d : one) { d.prob = p; pw.push_back(d); }
+            }
+            if ((rc = b->propw.alloc(sizeof(PropDev) * pw.size()))) return rc;
+            HIPCHK(hipMemcpy(b->propw.p, pw.data(), sizeof(PropDev) * pw.size(), hipMemcpyHostToDevice));
+            b->npropw = (int)pw.size();
+            b->kind = seg_env() == 0 ? 0 : 1;
+        }
+    }
     // io tables for V_j -> Z_j, and matvec tables Z_j -> W
     std::vector<IoDev> ios((size_t)kk * count);
     std::vector<MvDev> mvz((size_t)kk * count);
@@ -639,7 +738,8 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
     for (int j = 0; j < kk; ++j)
         for (int p = 0; p < count; ++p) {
             const int64_t blk = (int64_t)b->nrhs[p] * b->N[p];
-            ios[(size_t)j * count + p] = IoDev{V + b->voff[p] + j * blk, Z + b->zelem * (b->zoff[p] + j * blk), M[p]->fac.p};
+            ios[(size_t)j * count + p] =
+                IoDev{V + b->voff[p] + j * blk, Z + b->zelem * (b->zoff[p] + j * blk), M[p]->fac.p, M[p]->prop.p};
             mvz[(size_t)j * count + p] = MvDev{Z + b->zelem * (b->zoff[p] + j * blk), W + b->woff[p], nullptr, b->nrhs[p], 0};
         }
     if ((rc = b->io_sweep.alloc(sizeof(IoDev) * ios.size()))) return rc;
@@ -703,6 +803,11 @@ extern "C" int sweep_refactor_batch(helm_batch_t b, void* stream) {
         if (!launch_factor(B, b->prec, b->probs.as<ProbDev>(), b->fsubs.as<SubDev>(), b->nfsubs, b->fstatus.as<int>(), s))
             return fail(HELM_EINVAL, "no factor kernel for B=%d", B);
         LAUNCHCHK();
+        if (b->seg) {
+            if (!launch_prop(B, b->prec, b->probs.as<ProbDev>(), b->propw.as<PropDev>(), b->npropw, s))
+                return fail(HELM_EINVAL, "no propagator kernel for B=%d", B);
+            LAUNCHCHK();
+        }
         HIPCHK(hipStreamWaitEvent(s, b->ev_join, 0));
     }
     std::vector<int> st(b->count, 0);
@@ -752,9 +857,12 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int3
     const IoDev none{nullptr, nullptr, nullptr};
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
-        if (!run_chains(b->waves, b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
-                           b->spill.p, active, s))
-            return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
+        const bool ok = b->kind == 1
+                            ? launch_chains_seg(b->B, b->prec, 0, out_prec, 0, pd, b->segch.as<ChainDev>(), b->nsegch, io,
+                                                none, b->seg_wg, active, s)
+                            : run_chains(b->waves, b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd,
+                                         b->chains.as<ChainDev>(), b->nchains, io, none, b->spill.p, active, s);
+        if (!ok) return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
         LAUNCHCHK();
     }
     {
@@ -765,15 +873,19 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int3
     }
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
-        run_chains(b->waves, b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io, none,
-                      b->spill.p, active, s);
+        if (b->kind == 1)
+            launch_chains_seg(b->B, b->prec, 0, out_prec, 1, pd, b->segch.as<ChainDev>(), b->nsegch, io, none, b->seg_wg,
+                              active, s);
+        else
+            run_chains(b->waves, b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io,
+                       none, b->spill.p, active, s);
         LAUNCHCHK();
     }
     return HELM_OK;
 }
 
 extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32_t* ksplit, int32_t* waves,
-                               double* ms) {
+                               int32_t* segmented, double* ms) {
     if (!b) return fail(HELM_EINVAL, "NULL argument");
     if (reps < 1) reps = 1;
     hipStream_t s = (hipStream_t)stream;
@@ -786,31 +898,46 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    int best_ks = b->ks_chain, best_w = b->waves, rc = HELM_OK;
+    int best_ks = b->ks_chain, best_w = b->waves, best_kind = b->kind, rc = HELM_OK;
     double best = 1e300;
+    auto time_one = [&](double* per) -> int {
+        const IoDev* io = b->io_sweep.as<IoDev>();
+        int r = batch_sweep(b, io, zprec, nullptr, s);   // warm-up
+        if (r) return r;
+        if (hipEventRecord(e0, s) != hipSuccess) return fail(HELM_EHIP, "event record");
+        for (int k = 0; k < reps && r == HELM_OK; ++k) r = batch_sweep(b, io, zprec, nullptr, s);
+        if (r) return r;
+        float t = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+            return fail(HELM_EHIP, "event timing");
+        *per = (double)t / reps;
+        return HELM_OK;
+    };
+    if (b->seg) {
+        b->kind = 1;
+        double per = 0;
+        if ((rc = time_one(&per)) == HELM_OK && per < best) { best = per; best_kind = 1; }
+    }
+    b->kind = 0;
     for (int w = (B <= 17 ? 2 : 1); w >= 1 && rc == HELM_OK; --w)
         for (int ks = 1; ks <= q && rc == HELM_OK; ks *= 2) {
             if (q % ks) continue;
             if ((rc = build_chain_tables(b, ks, ksm))) break;
             b->waves = w;
-            const IoDev* io = b->io_sweep.as<IoDev>();
-            if ((rc = batch_sweep(b, io, zprec, nullptr, s))) break;   // warm-up
-            if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(HELM_EHIP, "event record"); break; }
-            for (int r = 0; r < reps && rc == HELM_OK; ++r) rc = batch_sweep(b, io, zprec, nullptr, s);
-            if (rc) break;
-            float t = 0.f;
-            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&t, e0, e1) != hipSuccess) { rc = fail(HELM_EHIP, "event timing"); break; }
-            const double per = (double)t / reps;
-            if (per < best) { best = per; best_ks = ks; best_w = w; }
+            double per = 0;
+            if ((rc = time_one(&per))) break;
+            if (per < best) { best = per; best_ks = ks; best_w = w; best_kind = 0; }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     if ((rc = build_chain_tables(b, best_ks, ksm))) return rc;
     b->waves = best_w;
-    if (ksplit) *ksplit = best_ks;
-    if (waves) *waves = best_w;
+    b->kind = best_kind;
+    if (ksplit) *ksplit = best_kind == 1 ? 0 : best_ks;
+    if (waves) *waves = best_kind == 1 ? 0 : best_w;
+    if (segmented) *segmented = best_kind;
     if (ms) *ms = best;
     return HELM_OK;
 }
@@ -821,7 +948,7 @@ extern "C" int sweep_apply_batch(helm_batch_t b, const void* const* f, void* con
     std::vector<IoDev> io(b->count);
     for (int p = 0; p < b->count; ++p) {
         if (!f[p] || !u[p]) return fail(HELM_EINVAL, "NULL vector for problem %d", p);
-        io[p] = IoDev{f[p], u[p], b->M[p]->fac.p};
+        io[p] = IoDev{f[p], u[p], b->M[p]->fac.p, b->M[p]->prop.p};
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemcpy(b->io_apply.p, io.data(), sizeof(IoDev) * b->count, hipMemcpyHostToDevice));

@@ -156,6 +156,21 @@ struct IoDev {
     const void* in;
     void* out;
     const void* fac;    // factor store of the problem (complex elements of the factor precision)
+    const void* prop;   // segment propagators of the problem's front strips (segmented sweep), or nullptr
+};
+
+// Columns per segment of the segmented strip solves.
+constexpr int SEG = 16;
+
+// One propagator work item: Q consecutive segments (from seg0) of one front strip.
+struct PropDev {
+    int32_t prob;           // index into the ProbDev table
+    int32_t cdir;           // column direction of the strip's block LU
+    int32_t rstep;          // 1/s2 of local row r at ris2[rstep * r]
+    int32_t seg0;
+    const void* fac;        // first stored column of the strip
+    const double2* ris2;
+    void* out;              // the strip's propagators: [segment][column-major, row-major][RP * RP]
 };
 
 __host__ __device__ constexpr int packed_size(int bs) { return bs * (bs + 1) / 2; }

@@ -67,6 +67,18 @@ bool launch_chains(int B, int prec, int in_prec, int out_prec, int phase, int ks
 bool launch_chains2(int B, int prec, int in_prec, int out_prec, int phase, int ksplit, const ProbDev* probs,
                     const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill,
                     const int32_t* active, hipStream_t s);
+// Segmented chains (strip solves partitioned into SEG-column segments): one workgroup of `waves`
+// waves per chain; ChainDev::pad_ = waves per right-hand side (ceil(segments / 4)), nq right-hand
+// sides per workgroup.  io[p].prop must hold the problem's propagators (launch_prop).  Returns false
+// for strip heights without an instance or a workgroup beyond the LDS.
+bool launch_chains_seg(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
+                       const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves,
+                       const int32_t* active, hipStream_t s);
+bool seg_supported(int B);
+// Largest workgroup (in waves) of the segmented chains that fits the LDS.
+int seg_max_waves(int prec, int B);
+// Segment propagators of front strips, one wave per work item (Q segments of one strip).
+bool launch_prop(int B, int prec, const ProbDev* probs, const PropDev* work, int nwork, hipStream_t s);
 bool launch_middle(int B, int prec, int in_prec, int out_prec, int ksplit, const ProbDev* probs,
                    const ChainDev* mids, int nmids, const IoDev* io, IoDev io_val, void* spill,
                    const int32_t* active, hipStream_t s);

@@ -1,0 +1,561 @@
+// a3 / a4 with every strip solve partitioned into column segments (a SPIKE-style two-level
+// recurrence; the paper solves each strip sequentially over its n columns, Algorithm 4).
+//
+// One strip solve (the forward / backward substitution of the block LU of the strip's quasi-1D
+// problem, block-tridiagonal over its columns in LU order t = 0..n-1) is the pair of affine
+// recurrences
+//   forward:  z_t = g_t + c_t,  w_t = Lambda_t^{-1} z_t,  c_{t+1} = -(E_t s2^{-1}) o w_t,  c_0 = 0
+//   backward: x_t = w_t + N_t x_{t+1},  N_t x = -E_t Lambda_t^{-1} (s2^{-1} o x),  x_n = 0
+// (c: the carry into the next column; E_t: the column's x1 coupling, s2^{-1}: the strip's row
+// factors).  With M_t = -diag(E_t s2^{-1}) Lambda_t^{-1} the carry obeys c_{t+1} = M_t (g_t + c_t),
+// and N_t = M_t^T because Lambda_t^{-1} is complex symmetric.
+// The n columns are cut into segments of SEG physical columns.  Over a segment the carry obeys
+// c_out = Phi c_in + q (Phi = product of the segment's M_t, q = the carry produced from a zero carry
+// in), and the backward map is x_top = Phi^T x_above + p.  A strip solve then runs, for every
+// segment at once (one 16-lane row group each):
+//   F1  forward pass from a zero carry          -> q             (also keeps g_t in registers)
+//   F2  the carries at the segment starts, sequentially over segments (one wave per right-hand side)
+//   F3  forward pass from the true carry       -> w_t           (registers)
+//   B1  backward pass from a zero value above   -> p
+//   B2  the values above the segments, sequentially over segments (Phi^T)
+//   B3  backward pass from the true value       -> x_t, the strip's outputs
+// so its sequential depth is about 4 SEG + 2 n / SEG steps instead of 2 n.  Consecutive strips of a
+// front are chained as in the plain sweep: the layer row of strip i feeds the right-hand side of
+// strip i + 1 column by column, and segment s of every strip covers the same physical columns, so
+// the row group that produces those values (B3) is the one that consumes them (F1 of the next strip).
+//
+// The propagators Phi of every segment of every strip are products of stored factor data only and
+// are formed after each factorisation (k_prop), in the factor precision, padded to RP x RP and stored
+// twice: column-major (read by F2) and row-major (read by B2), so both spine products load
+// contiguously.
+#include <algorithm>
+
+#include "hs_sweep_util.h"
+
+namespace hs {
+
+namespace {
+
+__device__ __forceinline__ void wg_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // vmcnt 63, expcnt 7, lgkmcnt 0: LDS writes done
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// first LU step of physical segment s (columns s*SEG+1 .. s*SEG+SEG) of a strip with column direction cd
+__host__ __device__ __forceinline__ int seg_tbase(int cd, int n, int s) { return cd > 0 ? s * SEG : n - s * SEG - SEG; }
+
+// acc += l * z_k for complex values, where z_k is lane k of this lane's 16-lane row (DPP row
+// broadcast as the first operand of each fused multiply-add: no LDS round trip for the vector).  The
+// leading s_nop covers the two wait states between a VALU write of z and its read through DPP.  Not
+// volatile: the compiler may schedule the loads of l ahead of it.
+template <int K>
+__device__ __forceinline__ void cfma_rowbcast(float& ax, float& ay, float lx, float ly, float zx, float zy) {
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %4, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%5, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %5, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
+        : "+v"(ax), "+v"(ay)
+        : "v"(lx), "v"(ly), "v"(zx), "v"(zy), "i"(K));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// propagators
+// ---------------------------------------------------------------------------------------------
+// One wave per (strip, group of Q segments); lane (q, r) holds row r of Phi of segment seg0 + q.
+// Phi <- M_t Phi over the segment's columns in LU order.
+template <class T, class TF, int BS>
+__global__ __launch_bounds__(64) void k_prop(const ProbDev* __restrict__ probs, const PropDev* __restrict__ work) {
+    using CT = C2<T>;
+    using CF = C2<TF>;
+    constexpr int RP = RowsOf<BS>::RP, Q = RowsOf<BS>::Q, PACK = packed_size(BS);
+    constexpr int STRIDE = col_stride<TF>(BS);
+    __shared__ CT phb[Q][BS][BS];
+    const PropDev W = work[blockIdx.x];
+    const int lane = threadIdx.x, r = lane % RP, q = lane / RP;
+    const int n = probs[W.prob].n;
+    const int S = (n + SEG - 1) / SEG;
+    const int seg = W.seg0 + q;
+    const bool rok = r < BS;
+    const int rr = rok ? r : 0;
+    const HS_GLOBAL CF* fac = gptr((const CF*)W.fac);
+    const CT is2 = ccast<T, double>(gld(gptr(W.ris2 + W.rstep * rr)));
+    const int tb = seg_tbase(W.cdir, n, seg);
+    CT ph[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) ph[c] = mk<T>(c == r ? 1 : 0, 0);
+    for (int j = 0; j < SEG; ++j) {
+        const int t = tb + j;
+        const bool valid = seg < S && t >= 0 && t < n;
+        const int tc = t < 0 ? 0 : (t >= n ? n - 1 : t);
+        const HS_GLOBAL CF* col = fac + (int64_t)tc * STRIDE;
+        if (rok) {
+#pragma unroll
+            for (int c = 0; c < BS; ++c) phb[q][r][c] = ph[c];
+        }
+        wave_sync();
+        const CT e = ccast<T, TF>(gld(col + PACK + XCOL_E));
+        const CT neps = cscale<T>(cmul<T>(e, is2), (T)-1);
+        CT l[BS];   // row rr of Lambda_t^{-1}
+#pragma unroll
+        for (int k = 0; k < BS; ++k) l[k] = ccast<T, TF>(gld(col + (k >= rr ? packed_index(BS, rr, k) : packed_index(BS, k, rr))));
+        // row r of M_t Phi, column by column (the previous Phi is read from LDS)
+#pragma unroll
+        for (int c = 0; c < BS; ++c) {
+            CT acc = mk<T>(0, 0);
+#pragma unroll
+            for (int k = 0; k < BS; ++k) acc = cfma<T>(l[k], phb[q][k][c], acc);
+            if (valid && rok) ph[c] = cmul<T>(neps, acc);
+        }
+        wave_sync();
+    }
+    if (rok) {
+#pragma unroll
+        for (int c = 0; c < BS; ++c) phb[q][r][c] = ph[c];
+    }
+    wave_sync();
+    if (seg < S) {
+        HS_GLOBAL CF* out = gptr((CF*)W.out) + (int64_t)seg * 2 * RP * RP;
+        const CF zero = mk<TF>(0, 0);
+#pragma unroll
+        for (int k = 0; k < RP; ++k) {
+            // column-major: entry (r, k) at k*RP + r; row-major: entry (k, r) at k*RP + r
+            gst(out + k * RP + r, (rok && k < BS) ? ccast<TF, T>(ph[k < BS ? k : 0]) : zero);
+            gst(out + RP * RP + k * RP + r, (rok && k < BS) ? ccast<TF, T>(phb[q][k < BS ? k : 0][rr]) : zero);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// segmented chains
+// ---------------------------------------------------------------------------------------------
+template <class T, class TF, int BS> struct SegShape {
+    static constexpr int RP = RowsOf<BS>::RP, Q = RowsOf<BS>::Q;
+    static constexpr int CB = col_stride<TF>(BS) * (int)sizeof(C2<TF>);   // bytes per stored column
+    static constexpr int N16 = CB / 16;
+    static constexpr int NCR = (N16 + RP - 1) / RP;                      // column chunks per lane
+    // LDS bytes per wave: staged columns, exchange vectors, 4 spine vectors per segment slot, layer rows
+    static constexpr int LDS_WAVE = Q * NCR * RP * 16 + 64 * (int)sizeof(C2<T>) + 4 * Q * RP * (int)sizeof(C2<T>) +
+                                    64 * (int)sizeof(C2<T>);
+};
+
+// Workgroups of up to 16 waves in FP32 (128 registers per lane) and 8 in FP64.
+template <class T> struct SegWaves { static constexpr int MAX = sizeof(T) == 8 ? 8 : 16; };
+
+template <class T, class TF, class TI, class TO, int BS, int MODE>
+__global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
+                                                 const IoDev* __restrict__ io, IoDev io_val,
+                                                 const int32_t* __restrict__ active) {
+    static_assert(MODE == MODE_FWD || MODE == MODE_BWD, "segmented chains serve the front phases");
+    using CT = C2<T>;
+    using CF = C2<TF>;
+    using SH = SegShape<T, TF, BS>;
+    constexpr int RP = SH::RP, Q = SH::Q, NCR = SH::NCR, CB = SH::CB;
+    static_assert(RP == 16, "segmented chains take strips of at most 16 rows");
+    constexpr int PACK = packed_size(BS);
+    constexpr int KJ = RP / Q;            // spine: entries of the k-sum per lane
+    constexpr int D = 2;                  // column prefetch distance in steps (divides SEG)
+    constexpr int PH = 2 * RP * RP;       // complex entries per stored segment propagator pair
+    static_assert(SEG % D == 0, "ring slots must repeat per phase");
+
+    extern __shared__ __align__(16) char smem[];
+    const int nw = blockDim.x >> 6;
+    chunk16* const colb = (chunk16*)smem;                        // [nw][Q][NCR*RP]
+    CT* const xz = (CT*)(colb + nw * Q * NCR * RP);              // [nw][64]
+    CT* const qv = xz + nw * 64;                                 // [nw*Q][RP], by segment slot
+    CT* const cv = qv + nw * Q * RP;
+    CT* const pv = cv + nw * Q * RP;
+    CT* const xv = pv + nw * Q * RP;
+    CT* const ylay = xv + nw * Q * RP;                           // [nw*64]: layer rows by column
+
+    const ChainDev ch = chains[blockIdx.x];
+    if (active && !any_active(active, ch)) return;               // whole workgroup
+    const ProbDev& P = probs[ch.prob];
+    const int n = P.n, B = P.B, cmid = P.c;
+    const int L = ch.front == 0 ? P.L_lo : P.L_up;
+    const int m = L;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane % RP, q = lane / RP;
+    const int Wr = ch.pad_;                    // waves per right-hand side
+    const int rl = wv / Wr, wr = wv - rl * Wr;
+    const bool live = rl < ch.nq;              // wave-uniform
+    if (!live) {
+        // no right-hand side for this wave: take part in every barrier of the chain, then leave
+        for (int b = 0; b < 4 * m + 4; ++b) wg_barrier();
+        return;
+    }
+    const IoDev IO = io ? io[ch.prob] : io_val;
+    const int S = (n + SEG - 1) / SEG;
+    const int seg = wr * Q + q;
+    const bool segok = seg < S;
+    const int sl = wv * Q + q;                 // this row group's segment slot
+    const int sbase = rl * Wr * Q;             // slot of segment 0 of this right-hand side
+    const bool spine = wr == 0;
+    const int sub0 = ch.front == 0 ? 0 : P.L_lo + 1;
+    const int64_t N = (int64_t)n * n;
+    const bool rok = r < BS;
+    const int rr = rok ? r : 0;
+    const bool slot = rok && r == B - 1;
+    const int rhs = ch.rhs0 + rl;
+    const HS_GLOBAL TI* __restrict__ fin = gptr((const TI*)IO.in + rhs * N);
+    HS_GLOBAL TO* __restrict__ y = gptr((TO*)IO.out + rhs * N);
+    const HS_GLOBAL char* const facbase = gptr((const char*)IO.fac);
+    const HS_GLOBAL CF* const propbase = gptr((const CF*)IO.prop);
+    CT* const ylr = ylay + rl * Wr * 64;       // this right-hand side's layer row, by column - 1
+    chunk16* const cb = colb + (wv * Q + q) * (NCR * RP);
+    const CF* const cf = (const CF*)cb;
+    CT* const xzq = xz + wv * 64 + q * RP;
+
+    const int dirF = ch.front == 0 ? 1 : -1;
+    const int jF = ch.front == 0 ? B : n + 1 - B;
+    auto strip_t = [&](int i) __attribute__((always_inline)) { return MODE == MODE_FWD ? i : L - i; };
+    auto strip_dir = [&](int i) __attribute__((always_inline)) -> int { return (strip_t(i) & 1) ? -1 : 1; };
+    auto strip_row = [&](int i) __attribute__((always_inline)) -> int {
+        const int jl = jF + dirF * strip_t(i);
+        return strip_t(i) == 0 ? jl - dirF * (B - 1 - rr) : jl;
+    };
+    CT is2_front, is2_other;
+    {
+        double2 s2, is2, lo, hi;
+        strip_profile(P, SUB_PHYS, jF - dirF * (B - 1), dirF, rr, s2, is2, lo, hi);
+        is2_front = ccast<T, double>(is2);
+        strip_profile(P, SUB_MOVE, 0, 1, rr, s2, is2, lo, hi);
+        is2_other = ccast<T, double>(is2);
+    }
+
+    int loff[BS];
+#pragma unroll
+    for (int k = 0; k < BS; ++k) loff[k] = k >= rr ? packed_index(BS, rr, k) : packed_index(BS, k, rr);
+    // Row rr of Lambda^{-1} (staged column) times the row group's vector, whose entry r is this
+    // lane's z: in FP32 through row broadcasts, in FP64 through the LDS exchange vector.  Every lane
+    // of the wave takes part (no divergent branch around it).
+    constexpr bool DPP = sizeof(T) == 4;
+    auto rowdot = [&](CT z) __attribute__((always_inline)) -> CT {
+        if constexpr (DPP) {
+            float a0x = 0.f, a0y = 0.f, a1x = 0.f, a1y = 0.f;
+            static_for<BS>([&](auto KC) __attribute__((always_inline)) {
+                constexpr int k = decltype(KC)::value;
+                const CT l = ccast<T, TF>(cf[loff[k]]);
+                if constexpr (k & 1) cfma_rowbcast<k>(a1x, a1y, l.x, l.y, z.x, z.y);
+                else cfma_rowbcast<k>(a0x, a0y, l.x, l.y, z.x, z.y);
+            });
+            return mk<T>(a0x + a1x, a0y + a1y);
+        } else {
+            xzq[r] = z;
+            wave_sync();
+            CT acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
+#pragma unroll
+            for (int k = 0; k < BS; ++k) {
+                const CT l = ccast<T, TF>(cf[loff[k]]);
+                if (k & 1) acc1 = cfma<T>(l, xzq[k], acc1);
+                else acc0 = cfma<T>(l, xzq[k], acc0);
+            }
+            return cadd<T>(acc0, acc1);
+        }
+    };
+    auto colscalar = [&](int which) __attribute__((always_inline)) -> CT { return ccast<T, TF>(cf[PACK + which]); };
+
+    // Per-strip sources: the strip's stored columns (buffer resource: out-of-range offsets read
+    // zeros), this row group's first LU step, column direction, input / output rows.
+    struct Src {
+        __amdgpu_buffer_rsrc_t col;
+        int tb, cd, row, st;
+        CT is2;
+    };
+    auto src_of = [&](int i) __attribute__((always_inline)) -> Src {
+        const int ic = i <= m ? i : m;
+        Src s;
+        s.st = strip_t(ic);
+        s.cd = strip_dir(ic);
+        s.tb = seg_tbase(s.cd, n, seg);
+        s.row = strip_row(ic);
+        s.is2 = s.st == 0 ? is2_front : is2_other;
+        s.col = buf_rsrc(facbase + sizeof(CF) * ((int64_t)(sub0 + s.st) * n * col_stride<TF>(BS)), (uint32_t)(n * CB));
+        return s;
+    };
+    auto colof = [&](const Src& s, int t) __attribute__((always_inline)) -> int {
+        const int tc = t < 0 ? 0 : (t >= n ? n - 1 : t);
+        return s.cd > 0 ? tc + 1 : n - tc;
+    };
+
+    // register ring: staged column chunks and one input value per step
+    chunk16 rk[D][NCR];
+    double2 ra[D];
+    // PK: 1 = F1, 3 = F3, 5 = B1, 7 = B3; j: step of the segment in LU order
+    auto issue = [&](auto PKC, auto JC, auto UC, const Src& s, bool first) __attribute__((always_inline)) {
+        constexpr int PK = decltype(PKC)::value, j = decltype(JC)::value, u = decltype(UC)::value;
+        const int t = s.tb + j;
+        const uint32_t vo = (uint32_t)t * (uint32_t)CB + (uint32_t)(r * 16);
+#pragma unroll
+        for (int c = 0; c < NCR; ++c) rk[u][c] = buf_ld16(s.col, vo + (uint32_t)(c * RP * 16), 0);
+        const int col = colof(s, t);
+        if constexpr (PK == 1) {
+            if (MODE == MODE_FWD) ra[u] = ld2(fin + (int64_t)(s.row - 1) * n + col - 1);
+            else if (first) ra[u] = ld2(y + (int64_t)(cmid - 1) * n + col - 1);
+        } else if constexpr (PK == 7) {
+            if (MODE == MODE_BWD) ra[u] = ld2(y + (int64_t)(s.row - 1) * n + col - 1);
+        }
+    };
+    auto stage = [&](int u) __attribute__((always_inline)) {
+#pragma unroll
+        for (int c = 0; c < NCR; ++c) cb[r + c * RP] = rk[u][c];
+    };
+
+    CT gw[SEG];
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) gw[j] = mk<T>(0, 0);
+    CT carry = mk<T>(0, 0), xb = mk<T>(0, 0);
+
+    // one forward step: F1 (PK 1) builds g_t from the input and the previous layer row, F3 (PK 3)
+    // takes it from registers and leaves w_t there
+    auto fstep = [&](auto PKC, auto JC, const Src& s, bool first, bool full) __attribute__((always_inline)) {
+        constexpr int PK = decltype(PKC)::value, j = decltype(JC)::value, u = j % D;
+        const int t = s.tb + j;
+        const bool valid = segok && t >= 0 && t < n;
+        stage(u);
+        wave_sync();
+        CT g;
+        if constexpr (PK == 1) {
+            const int col = colof(s, t);
+            if (MODE == MODE_FWD) {
+                CT gv = ccast<T, double>(ra[u]);
+                if (!full) gv = csub<T>(gv, cmul<T>(colscalar(XCOL_APREV), ylr[col - 1]));
+                g = (full ? rok : slot) ? gv : mk<T>(0, 0);
+            } else {
+                const CT yp = first ? ccast<T, double>(ra[u]) : ylr[col - 1];
+                g = slot ? cmul<T>(colscalar(XCOL_ANEXT), yp) : mk<T>(0, 0);
+            }
+            gw[j] = g;
+        } else {
+            g = gw[j];
+        }
+        const CT w = rowdot(csel<T>(rok, cadd<T>(g, carry), mk<T>(0, 0)));
+        const CT ne = cscale<T>(cmul<T>(colscalar(XCOL_E), s.is2), (T)-1);
+        if constexpr (PK == 3) gw[j] = w;
+        carry = csel<T>(valid, cmul<T>(ne, w), carry);
+        wave_sync();
+    };
+    // one backward step: B1 (PK 5) from a zero value above, B3 (PK 7) writes the strip's outputs
+    auto bstep = [&](auto PKC, auto JC, const Src& s, bool full) __attribute__((always_inline)) {
+        constexpr int PK = decltype(PKC)::value, j = decltype(JC)::value;
+        constexpr int u = (SEG - 1 - j) % D;
+        const int t = s.tb + j;
+        const bool valid = segok && t >= 0 && t < n;
+        stage(u);
+        wave_sync();
+        const CT v = rowdot(csel<T>(rok, cmul<T>(s.is2, xb), mk<T>(0, 0)));
+        const CT xn = cfms<T>(colscalar(XCOL_E), v, gw[j]);
+        xb = csel<T>(valid, xn, xb);
+        if constexpr (PK == 7) {
+            const int col = colof(s, t);
+            const CT yval = MODE == MODE_BWD ? csub<T>(ccast<T, double>(ra[u]), xb) : xb;
+            if (valid && (full ? rok : slot)) gst(y + (int64_t)(s.row - 1) * n + col - 1, cvt_out<TO, T>(yval));
+            if (valid && slot) ylr[col - 1] = yval;
+        }
+        wave_sync();
+    };
+
+    // Phases.  Every step refills its ring slot with the step D later in the sequence
+    // F3(i) B1(i) B3(i) F1(i+1) F3(i+1) ...
+    auto phase_f = [&](auto PKC, const Src& s, bool first, auto NPKC, const Src& ns, bool nfirst) __attribute__((always_inline)) {
+        const bool full = s.st == 0;
+        static_for<SEG>([&](auto JC) __attribute__((always_inline)) {
+            constexpr int j = decltype(JC)::value;
+            fstep(PKC, JC, s, first, full);
+            constexpr int u = j % D;
+            if constexpr (j + D < SEG) issue(PKC, std::integral_constant<int, j + D>{}, std::integral_constant<int, u>{}, s, first);
+            else {
+                // next phase: a backward phase (F3 -> B1) starts at j = SEG-1; a forward one (F1 -> F3) at 0
+                constexpr int NPK = decltype(NPKC)::value;
+                constexpr int k = j + D - SEG;
+                constexpr int nj = (NPK == 5 || NPK == 7) ? SEG - 1 - k : k;
+                issue(NPKC, std::integral_constant<int, nj>{}, std::integral_constant<int, u>{}, ns, nfirst);
+            }
+        });
+    };
+    auto phase_b = [&](auto PKC, const Src& s, auto NPKC, const Src& ns, bool nfirst) __attribute__((always_inline)) {
+        const bool full = s.st == 0;
+        static_for<SEG>([&](auto KC) __attribute__((always_inline)) {
+            constexpr int k = decltype(KC)::value;      // position in the phase
+            constexpr int j = SEG - 1 - k;
+            bstep(PKC, std::integral_constant<int, j>{}, s, full);
+            constexpr int u = k % D;
+            if constexpr (k + D < SEG) issue(PKC, std::integral_constant<int, j - D>{}, std::integral_constant<int, u>{}, s, false);
+            else {
+                constexpr int NPK = decltype(NPKC)::value;
+                constexpr int kk = k + D - SEG;
+                constexpr int nj = (NPK == 5 || NPK == 7) ? SEG - 1 - kk : kk;
+                issue(NPKC, std::integral_constant<int, nj>{}, std::integral_constant<int, u>{}, ns, nfirst);
+            }
+        });
+    };
+    auto prime = [&](auto PKC, const Src& s, bool first) __attribute__((always_inline)) {
+        static_for<D>([&](auto UC) __attribute__((always_inline)) {
+            constexpr int u = decltype(UC)::value;
+            issue(PKC, std::integral_constant<int, u>{}, UC, s, first);
+        });
+    };
+
+    // Spines: one wave per right-hand side; lane (q, r) sums k = jj*Q + q, the row groups are combined
+    // with cross-row sums.  Propagators of later segments are prefetched DS steps ahead.
+    constexpr int DS = 2;
+    auto spine_run = [&](int i, bool fwd) __attribute__((always_inline)) {
+        const Src s = src_of(i);
+        const HS_GLOBAL CF* const ph = propbase + (int64_t)(sub0 + s.st) * S * PH + (fwd ? 0 : RP * RP);
+        CT* const vin = fwd ? qv : pv;     // segment contributions
+        CT* const vout = fwd ? cv : xv;    // value entering each segment
+        auto sidx = [&](int k) __attribute__((always_inline)) -> int {
+            const int kc = k < S ? k : S - 1;
+            return (fwd == (s.cd > 0)) ? kc : S - 1 - kc;
+        };
+        CT pr[DS][KJ];
+        auto pload = [&](int u, int k) __attribute__((always_inline)) {
+            const HS_GLOBAL CF* p = ph + (int64_t)sidx(k) * PH + q * RP + r;
+#pragma unroll
+            for (int jj = 0; jj < KJ; ++jj) pr[u][jj] = ccast<T, TF>(gld(p + jj * Q * RP));
+        };
+        static_for<DS>([&](auto UC) __attribute__((always_inline)) { pload(decltype(UC)::value, decltype(UC)::value); });
+        CT v = mk<T>(0, 0);
+        for (int kb = 0; kb < S; kb += DS) {
+            static_for<DS>([&](auto UC) __attribute__((always_inline)) {
+                constexpr int u = decltype(UC)::value;
+                const int k = kb + u;
+                if (k < S) {
+                    const int si = sidx(k);
+                    CT* const vo = vout + (sbase + si) * RP;
+                    if (q == 0) vo[r] = v;
+                    wave_sync();
+                    CT acc = mk<T>(0, 0);
+#pragma unroll
+                    for (int jj = 0; jj < KJ; ++jj) acc = cfma<T>(pr[u][jj], vo[jj * Q + q], acc);
+                    acc.x = xor_sum<16>(acc.x);
+                    acc.y = xor_sum<16>(acc.y);
+                    acc.x = xor_sum<32>(acc.x);
+                    acc.y = xor_sum<32>(acc.y);
+                    v = cadd<T>(acc, vin[(sbase + si) * RP + r]);
+                    wave_sync();
+                    pload(u, k + DS);
+                }
+            });
+        }
+    };
+
+    // prologue: F1 of strip 0, its spine
+    Src sc = src_of(0), sn = src_of(1);
+    prime(std::integral_constant<int, 1>{}, sc, true);
+    phase_f(std::integral_constant<int, 1>{}, sc, true, std::integral_constant<int, 3>{}, sc, false);
+    qv[sl * RP + r] = csel<T>(rok, carry, mk<T>(0, 0));
+    wg_barrier();
+    if (spine) spine_run(0, true);
+    wg_barrier();
+    for (int i = 0; i <= m; ++i) {
+        carry = cv[sl * RP + r];
+        phase_f(std::integral_constant<int, 3>{}, sc, false, std::integral_constant<int, 5>{}, sc, false);
+        carry = mk<T>(0, 0);
+        xb = mk<T>(0, 0);
+        phase_b(std::integral_constant<int, 5>{}, sc, std::integral_constant<int, 7>{}, sc, false);
+        pv[sl * RP + r] = csel<T>(rok, xb, mk<T>(0, 0));
+        wg_barrier();
+        if (spine) spine_run(i, false);
+        wg_barrier();
+        xb = xv[sl * RP + r];
+        phase_b(std::integral_constant<int, 7>{}, sc, std::integral_constant<int, 1>{}, sn, false);
+        if (i < m) {
+            carry = mk<T>(0, 0);
+            phase_f(std::integral_constant<int, 1>{}, sn, false, std::integral_constant<int, 3>{}, sn, false);
+            qv[sl * RP + r] = csel<T>(rok, carry, mk<T>(0, 0));
+            wg_barrier();
+            if (spine) spine_run(i + 1, true);
+            wg_barrier();
+        }
+        sc = sn;
+        sn = src_of(i + 2);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------------------------
+bool seg_supported(int B) { return B == 4 || B == 5 || B == 7 || B == 9 || B == 13; }
+
+template <class T, class TF> static int seg_waves_typed(int B) {
+    int per = 0;
+    switch (B) {
+        case 4: per = SegShape<T, TF, 4>::LDS_WAVE; break;
+        case 5: per = SegShape<T, TF, 5>::LDS_WAVE; break;
+        case 7: per = SegShape<T, TF, 7>::LDS_WAVE; break;
+        case 9: per = SegShape<T, TF, 9>::LDS_WAVE; break;
+        case 13: per = SegShape<T, TF, 13>::LDS_WAVE; break;
+        default: return 0;
+    }
+    return std::min(SegWaves<T>::MAX, (160 * 1024) / per);
+}
+int seg_max_waves(int prec, int B) { return prec == 0 ? seg_waves_typed<double, double>(B) : seg_waves_typed<float, float>(B); }
+
+template <class T, class TF, class TI, class TO, int BV, int MODE>
+static bool segp_launch(const ProbDev* probs, const ChainDev* chains, int nb, const IoDev* io, IoDev iov, int waves,
+                        const int32_t* act, hipStream_t s) {
+    const size_t lds = (size_t)SegShape<T, TF, BV>::LDS_WAVE * waves;
+    if (lds > 160 * 1024) return false;
+    hipLaunchKernelGGL((k_sweepP<T, TF, TI, TO, BV, MODE>), dim3(nb), dim3(64 * waves), lds, s, probs, chains, io, iov, act);
+    return true;
+}
+
+template <class T, class TF, class TI, class TO, int MODE>
+static bool segp_typed(int bs, const ProbDev* probs, const ChainDev* chains, int nb, const IoDev* io, IoDev iov,
+                       int waves, const int32_t* act, hipStream_t s) {
+    switch (bs) {
+#define HS_CASE(BV) \
+    case BV: return segp_launch<T, TF, TI, TO, BV, MODE>(probs, chains, nb, io, iov, waves, act, s);
+        HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13)
+#undef HS_CASE
+        default: return false;
+    }
+}
+
+template <int MODE>
+static bool segp_prec(int bs, int prec, int in_prec, int out_prec, const ProbDev* probs, const ChainDev* chains, int nb,
+                      const IoDev* io, IoDev iov, int waves, const int32_t* act, hipStream_t s) {
+    if (prec == 0) {
+        if (in_prec == 0 && out_prec == 0)
+            return segp_typed<double, double, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, s);
+        return false;
+    }
+    if (in_prec == 0 && out_prec == 0)
+        return segp_typed<float, float, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, s);
+    if (in_prec == 0 && out_prec == 1)
+        return segp_typed<float, float, double2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, s);
+    if (in_prec == 1 && out_prec == 1)
+        return segp_typed<float, float, float2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, s);
+    return false;
+}
+
+bool launch_chains_seg(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
+                       const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves,
+                       const int32_t* active, hipStream_t s) {
+    if (nchains <= 0) return true;
+    if (waves < 1 || waves > seg_max_waves(prec, B)) return false;
+    return phase == 0 ? segp_prec<MODE_FWD>(B, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, waves, active, s)
+                      : segp_prec<MODE_BWD>(B, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, waves, active, s);
+}
+
+template <class T, class TF>
+static bool prop_typed(int bs, const ProbDev* probs, const PropDev* work, int nwork, hipStream_t s) {
+    switch (bs) {
+#define HS_CASE(BV) \
+    case BV: hipLaunchKernelGGL((k_prop<T, TF, BV>), dim3(nwork), dim3(64), 0, s, probs, work); return true;
+        HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13)
+#undef HS_CASE
+        default: return false;
+    }
+}
+
+bool launch_prop(int B, int prec, const ProbDev* probs, const PropDev* work, int nwork, hipStream_t s) {
+    if (nwork <= 0) return true;
+    return prec == 0 ? prop_typed<double, double>(B, probs, work, nwork, s) : prop_typed<float, float>(B, probs, work, nwork, s);
+}
+
+}  // namespace hs

@@ -69,7 +69,7 @@ def _load() -> C.CDLL:
         "sweep_apply_batch": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), vp]),
         "sweep_refactor_batch": (C.c_int, [vp, vp]),
         "helm_batch_tune": (C.c_int, [vp, C.c_int32, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                      C.POINTER(C.c_double)]),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "helm_free": (None, [vp]),
         "sweep_free": (None, [vp]),
         "helm_batch_free": (None, [vp]),
@@ -341,11 +341,12 @@ class Batch:
     def tune(self, reps: int = 2, stream=None) -> dict:
         """Pick the fastest sweep schedule for this batch by timing every candidate (a7 autotuner).
 
-        Overwrites the batch's Krylov work space.  Returns {"ksplit", "waves", "ms_per_apply"}."""
-        ks, wv, ms = C.c_int32(), C.c_int32(), C.c_double()
+        Overwrites the batch's Krylov work space.  Returns {"segmented", "ksplit", "waves", "ms_per_apply"}
+        (ksplit / waves describe the plain chains and are 0 when the segmented chains won)."""
+        ks, wv, sg, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
         _check(_lib.helm_batch_tune(self._h, int(reps), C.c_void_p(_stream(stream)), C.byref(ks), C.byref(wv),
-                                    C.byref(ms)))
-        return {"ksplit": ks.value, "waves": wv.value, "ms_per_apply": ms.value}
+                                    C.byref(sg), C.byref(ms)))
+        return {"segmented": sg.value, "ksplit": ks.value, "waves": wv.value, "ms_per_apply": ms.value}
 
     def refactor(self, stream=None):
         """Recompute the factors of every member in place (a2 over the whole batch, two launches)."""

@@ -300,6 +300,7 @@ def test_batch_refactor_equals_individual(hs, torch, prec):
 def test_sweep_ksplit_parity(hs, torch, monkeypatch, ks, prec, waves):
     """Every right-hand-side grouping of the sweep waves (row-dot products split 1, 2 or 4 ways), with
     one or two waves per chain, gives the oracle's M f, for a single problem and for an uneven batch."""
+    monkeypatch.setenv("HELM_SWEEP_SEG", "0")
     monkeypatch.setenv("HELM_SWEEP_KSPLIT", str(ks))
     monkeypatch.setenv("HELM_SWEEP_WAVES", str(waves))
     _log("ksplit", ks, "prec", prec, "waves", waves)
@@ -354,7 +355,79 @@ def test_batch_tune_keeps_results(hs, torch):
     b = hs.Batch(probs, facs, [R for _, R in specs], restart=4)
     choice = b.tune(reps=1)
     _log("tuned", choice)
-    assert choice["waves"] in (1, 2) and choice["ksplit"] in (1, 2, 4) and choice["ms_per_apply"] > 0
+    assert choice["ms_per_apply"] > 0
+    assert choice["segmented"] == 1 or (choice["waves"] in (1, 2) and choice["ksplit"] in (1, 2, 4))
     ub = b.apply([torch.as_tensor(f, device="cuda") for f in fs])
     for u, f, Mo in zip(ub, fs, mos):
         assert _rel(u.cpu().numpy(), OS.apply_sweep(Mo, f)) <= 1e-10
+
+
+# (n, moving-PML width): strip heights 4, 5, 7, 9, 13; ragged last segments and exact multiples of
+# the 16-column segment; a single segment (n < 16 is below the minimum size, n = 33 has three)
+SEG_CASES = [(47, 3), (64, 4), (100, 6), (33, 8), (129, 8), (40, 12), (160, 12), (255, 12)]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n,w", SEG_CASES)
+def test_sweep_segmented_parity(hs, torch, monkeypatch, n, w, prec):
+    """The segmented chains (every strip solve split into 16-column segments joined through segment
+    propagators) give the oracle's M f, alone and inside an uneven batch whose workgroups hold
+    different numbers of right-hand sides."""
+    monkeypatch.setenv("HELM_SWEEP_SEG", "1")
+    _log("segmented", n, w, "prec", prec)
+    op = OH.Params(n=n, omega=2 * math.pi * n / 8, alpha=2.0, pml_w=w, mpml_w=w)
+    c = workloads.velocity_layered(n, seed=n + 17)
+    A = _gpu_problem(hs, torch, op, c)
+    F = hs.Factors(A, prec)
+    Mo = OS.factor(op, c)
+    f = workloads.random_rhs(n, 3, seed=n + 5)
+    fd = torch.as_tensor(f, device="cuda")
+    if prec == hs.HELM_C64:
+        u = F.apply(fd.to(torch.complex64)).cpu().numpy().astype(np.complex128)
+        uo = OS.apply_sweep(Mo, f.astype(np.complex64).astype(np.complex128))
+        tol = 1e-4
+    else:
+        u = F.apply(fd).cpu().numpy()
+        uo = OS.apply_sweep(Mo, f)
+        tol = 1e-10
+    err = _rel(u, uo)
+    _log(f"  single rel {err:.2e}")
+    assert err <= tol
+    # batch: next to a smaller problem of the same strip height (fewer segments, so more
+    # right-hand sides per workgroup), 3 and 5 right-hand sides
+    n2 = max(2 * (w + 1) + 3, n // 2 + 1)
+    op2 = OH.Params(n=n2, omega=2 * math.pi * n2 / 8, alpha=2.0, pml_w=w, mpml_w=w)
+    c2 = workloads.velocity_layered(n2, seed=n2 + 3)
+    A2 = _gpu_problem(hs, torch, op2, c2)
+    F2 = hs.Factors(A2, prec)
+    f2 = workloads.random_rhs(n2, 5, seed=n2 + 9)
+    b = hs.Batch([A, A2], [F, F2], [3, 5], restart=4)
+    ub = b.apply([fd, torch.as_tensor(f2, device="cuda")])
+    btol = 1e-10 if prec == 0 else 1e-4
+    e1 = _rel(ub[0].cpu().numpy(), OS.apply_sweep(Mo, f))
+    e2 = _rel(ub[1].cpu().numpy(), OS.apply_sweep(OS.factor(op2, c2), f2))
+    _log(f"  batch rel {e1:.2e} {e2:.2e}")
+    assert e1 <= btol and e2 <= btol
+
+
+def test_sweep_segmented_equals_chains(hs, torch, monkeypatch):
+    """On the bench's strip height and a ragged n, a batched FGMRES solve (which freezes converged
+    systems) takes the same iterations with the segmented and the plain chains, to the same answer."""
+    n, w = 255, 12
+    op = OH.Params(n=n, omega=2 * math.pi * n / 8, alpha=2.0, pml_w=w, mpml_w=w)
+    c = workloads.velocity_layered(n, seed=5)
+    f = torch.as_tensor(workloads.random_rhs(n, 4, seed=6), device="cuda")
+    sols = []
+    for seg in ("0", "1"):
+        monkeypatch.setenv("HELM_SWEEP_SEG", seg)
+        A = _gpu_problem(hs, torch, op, c)
+        F = hs.Factors(A, hs.HELM_C64)
+        b = hs.Batch([A], [F], [4], restart=20)
+        res = b.solve([f], tol=1e-6, maxit=200)
+        sols.append(res)
+        _log("seg", seg, res.iters, res.relres)
+    r0, r1 = sols
+    assert r0.converged and r1.converged
+    assert all(abs(a - c) <= 1 for a, c in zip(r0.iters, r1.iters))
+    # both solutions meet the 1e-6 residual; they agree to that level times the conditioning
+    assert _rel(r1.u[0].cpu().numpy(), r0.u[0].cpu().numpy()) <= 1e-4
