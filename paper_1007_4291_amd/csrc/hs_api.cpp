@@ -460,6 +460,12 @@ static void rhs_grouping(int B, int max_nrhs, int* Q, int* ks, int* Qm, int* ksm
 
 // Segmented chain table: every workgroup has wg waves; problem p (largest first) gives each
 // right-hand side seg_waves_rhs(n_p) of them, wg / that right-hand sides per workgroup and front.
+// Workgroups are dealt to the 8 XCDs round-robin by index, so the table is laid out per XCD: all
+// workgroups of one (problem, front) -- which read the same factor columns and propagators at about
+// the same time -- get indices of one residue mod 8 and share that XCD's L2.  (problem, front) groups
+// go, largest first, to the XCD with the least work so far; shorter XCD queues are padded with
+// entries of no right-hand side (nq = 0), which return at once.  HELM_SEG_XCD=0 keeps the plain order.
+constexpr int kXcds = 8;
 static std::vector<ChainDev> seg_table(const std::vector<int>& n, const std::vector<int>& nrhs, int* wg) {
     const int count = (int)n.size();
     int w = 1;
@@ -467,14 +473,37 @@ static std::vector<ChainDev> seg_table(const std::vector<int>& n, const std::vec
     std::vector<int> order(count), base(count + 1, 0);
     for (int p = 0; p < count; ++p) { order[p] = p; base[p + 1] = base[p] + nrhs[p]; }
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n[a] > n[c]; });
-    std::vector<ChainDev> ch;
+    std::vector<std::vector<ChainDev>> groups;
+    std::vector<double> work;
     for (int p : order) {
         const int wr = seg_waves_rhs(n[p]), R = std::max(1, w / wr);
-        for (int g = 0; g * R < nrhs[p]; ++g)
-            for (int f = 0; f < 2; ++f)
-                ch.push_back(ChainDev{p, f, g * R, std::min(R, nrhs[p] - g * R), base[p] + g * R, wr, 0});
+        for (int f = 0; f < 2; ++f) {
+            std::vector<ChainDev> g;
+            for (int k = 0; k * R < nrhs[p]; ++k)
+                g.push_back(ChainDev{p, f, k * R, std::min(R, nrhs[p] - k * R), base[p] + k * R, wr, 0});
+            groups.push_back(g);
+            work.push_back((double)n[p] * n[p] * (double)g.size());
+        }
     }
     *wg = w;
+    const char* e = std::getenv("HELM_SEG_XCD");
+    std::vector<ChainDev> ch;
+    if (e && std::atoi(e) == 0) {
+        for (auto& g : groups) ch.insert(ch.end(), g.begin(), g.end());
+        return ch;
+    }
+    std::vector<std::vector<ChainDev>> q(kXcds);
+    std::vector<double> load(kXcds, 0.0);
+    for (size_t i = 0; i < groups.size(); ++i) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        q[x].insert(q[x].end(), groups[i].begin(), groups[i].end());
+        load[x] += work[i];
+    }
+    size_t len = 0;
+    for (auto& v : q) len = std::max(len, v.size());
+    for (size_t i = 0; i < len; ++i)
+        for (int x = 0; x < kXcds; ++x)
+            ch.push_back(i < q[x].size() ? q[x][i] : ChainDev{0, 0, 0, 0, 0, 1, 0});
     return ch;
 }
 

@@ -138,8 +138,13 @@ template <class T, class TF, int BS> struct SegShape {
     static constexpr int CB = col_stride<TF>(BS) * (int)sizeof(C2<TF>);   // bytes per stored column
     static constexpr int N16 = CB / 16;
     static constexpr int NCR = (N16 + RP - 1) / RP;                      // column chunks per lane
+    // chunks per row group's staged column: 64 bytes of padding shift the row groups of a half wave
+    // to other LDS banks (the packed-row reads of neighbouring row groups otherwise collide)
+    static constexpr int CSTR = NCR * RP + 4;
+    // exchange vectors: LDS only in FP64 (FP32 takes the vector through row broadcasts)
+    static constexpr int XZ = sizeof(T) == 8 ? 64 : 0;
     // LDS bytes per wave: staged columns, exchange vectors, 4 spine vectors per segment slot, layer rows
-    static constexpr int LDS_WAVE = Q * NCR * RP * 16 + 64 * (int)sizeof(C2<T>) + 4 * Q * RP * (int)sizeof(C2<T>) +
+    static constexpr int LDS_WAVE = Q * CSTR * 16 + XZ * (int)sizeof(C2<T>) + 4 * Q * RP * (int)sizeof(C2<T>) +
                                     64 * (int)sizeof(C2<T>);
 };
 
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     using CT = C2<T>;
     using CF = C2<TF>;
     using SH = SegShape<T, TF, BS>;
-    constexpr int RP = SH::RP, Q = SH::Q, NCR = SH::NCR, CB = SH::CB;
+    constexpr int RP = SH::RP, Q = SH::Q, NCR = SH::NCR, CB = SH::CB, CSTR = SH::CSTR;
     static_assert(RP == 16, "segmented chains take strips of at most 16 rows");
     constexpr int PACK = packed_size(BS);
     constexpr int KJ = RP / Q;            // spine: entries of the k-sum per lane
@@ -164,15 +169,16 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
 
     extern __shared__ __align__(16) char smem[];
     const int nw = blockDim.x >> 6;
-    chunk16* const colb = (chunk16*)smem;                        // [nw][Q][NCR*RP]
-    CT* const xz = (CT*)(colb + nw * Q * NCR * RP);              // [nw][64]
-    CT* const qv = xz + nw * 64;                                 // [nw*Q][RP], by segment slot
+    chunk16* const colb = (chunk16*)smem;                        // [nw][Q][CSTR]
+    CT* const xz = (CT*)(colb + nw * Q * CSTR);                  // [nw][XZ]
+    CT* const qv = xz + nw * SH::XZ;                             // [nw*Q][RP], by segment slot
     CT* const cv = qv + nw * Q * RP;
     CT* const pv = cv + nw * Q * RP;
     CT* const xv = pv + nw * Q * RP;
     CT* const ylay = xv + nw * Q * RP;                           // [nw*64]: layer rows by column
 
     const ChainDev ch = chains[blockIdx.x];
+    if (ch.nq == 0) return;                                      // padding entry of the table
     if (active && !any_active(active, ch)) return;               // whole workgroup
     const ProbDev& P = probs[ch.prob];
     const int n = P.n, B = P.B, cmid = P.c;
@@ -205,9 +211,9 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     const HS_GLOBAL char* const facbase = gptr((const char*)IO.fac);
     const HS_GLOBAL CF* const propbase = gptr((const CF*)IO.prop);
     CT* const ylr = ylay + rl * Wr * 64;       // this right-hand side's layer row, by column - 1
-    chunk16* const cb = colb + (wv * Q + q) * (NCR * RP);
+    chunk16* const cb = colb + (wv * Q + q) * CSTR;
     const CF* const cf = (const CF*)cb;
-    CT* const xzq = xz + wv * 64 + q * RP;
+    CT* const xzq = xz + wv * SH::XZ + q * RP;
 
     const int dirF = ch.front == 0 ? 1 : -1;
     const int jF = ch.front == 0 ? B : n + 1 - B;
@@ -263,6 +269,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     struct Src {
         __amdgpu_buffer_rsrc_t col;
         int tb, cd, row, st;
+        uint32_t vb;                 // byte offset of this lane's chunk 0 of column tb
         CT is2;
     };
     auto src_of = [&](int i) __attribute__((always_inline)) -> Src {
@@ -272,9 +279,17 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         s.cd = strip_dir(ic);
         s.tb = seg_tbase(s.cd, n, seg);
         s.row = strip_row(ic);
+        s.vb = (uint32_t)s.tb * (uint32_t)CB + (uint32_t)(r * 16);
         s.is2 = s.st == 0 ? is2_front : is2_other;
         s.col = buf_rsrc(facbase + sizeof(CF) * ((int64_t)(sub0 + s.st) * n * col_stride<TF>(BS)), (uint32_t)(n * CB));
         return s;
+    };
+    // A step's addresses are formed where they are used: the unrolled phases would otherwise keep
+    // every step's offsets live from the top of the strip loop (and spill them).  The empty asm makes
+    // the per-strip value opaque at that point.
+    auto late = [](auto v) __attribute__((always_inline)) {
+        asm volatile("" : "+v"(v));
+        return v;
     };
     auto colof = [&](const Src& s, int t) __attribute__((always_inline)) -> int {
         const int tc = t < 0 ? 0 : (t >= n ? n - 1 : t);
@@ -287,10 +302,10 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     // PK: 1 = F1, 3 = F3, 5 = B1, 7 = B3; j: step of the segment in LU order
     auto issue = [&](auto PKC, auto JC, auto UC, const Src& s, bool first) __attribute__((always_inline)) {
         constexpr int PK = decltype(PKC)::value, j = decltype(JC)::value, u = decltype(UC)::value;
-        const int t = s.tb + j;
-        const uint32_t vo = (uint32_t)t * (uint32_t)CB + (uint32_t)(r * 16);
+        const uint32_t vo = late(s.vb) + (uint32_t)(j * CB);
 #pragma unroll
         for (int c = 0; c < NCR; ++c) rk[u][c] = buf_ld16(s.col, vo + (uint32_t)(c * RP * 16), 0);
+        const int t = late(s.tb) + j;
         const int col = colof(s, t);
         if constexpr (PK == 1) {
             if (MODE == MODE_FWD) ra[u] = ld2(fin + (int64_t)(s.row - 1) * n + col - 1);
@@ -313,7 +328,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     // takes it from registers and leaves w_t there
     auto fstep = [&](auto PKC, auto JC, const Src& s, bool first, bool full) __attribute__((always_inline)) {
         constexpr int PK = decltype(PKC)::value, j = decltype(JC)::value, u = j % D;
-        const int t = s.tb + j;
+        const int t = late(s.tb) + j;
         const bool valid = segok && t >= 0 && t < n;
         stage(u);
         wave_sync();
@@ -342,7 +357,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     auto bstep = [&](auto PKC, auto JC, const Src& s, bool full) __attribute__((always_inline)) {
         constexpr int PK = decltype(PKC)::value, j = decltype(JC)::value;
         constexpr int u = (SEG - 1 - j) % D;
-        const int t = s.tb + j;
+        const int t = late(s.tb) + j;
         const bool valid = segok && t >= 0 && t < n;
         stage(u);
         wave_sync();
