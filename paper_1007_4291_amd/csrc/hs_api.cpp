@@ -138,7 +138,7 @@ struct sweep_factors_s {
     std::vector<SubDev> hsubs;
     std::vector<int> sub_rows;
     // single-problem chain tables (rebuilt when nrhs changes)
-    DevBuf chains, mids, segch;
+    DevBuf chains, mids, segch, segws;
     int chains_nrhs = -1, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1, waves = 1;
     int nsegch = 0, seg_wg = 0, kind = 0;   // kind 1: segmented chains
     helm_batch_t solo = nullptr;    // cached batch of one for fgmres_solve
@@ -165,7 +165,7 @@ struct helm_batch_s {
     DevBuf fsubs, msubs, fstatus;
     int nfsubs = 0, nmsubs = 0;
     // segmented sweep: propagator work of all problems, chain table, workgroup waves; kind 1 selects it
-    DevBuf propw, segch;
+    DevBuf propw, segch, segws;
     int npropw = 0, nsegch = 0, seg_wg = 0, kind = 0;
     bool seg = false;
     hipStream_t side = nullptr;
@@ -293,8 +293,9 @@ extern "C" int helm_matvec(helm_problem_t A, const void* x, int32_t x_prec, void
 // Segmented sweep sizes: segments per strip, waves per right-hand side (4 segments per wave).
 static int seg_count(int n) { return (n + SEG - 1) / SEG; }
 static int seg_waves_rhs(int n) { return (seg_count(n) + 3) / 4; }
-// Propagator pair (column- and row-major RP x RP blocks) per segment, complex elements.
-constexpr int64_t kSegPH = 2 * 16 * 16;
+// Segment propagators of one strip: a row-major B x B block per segment, the strip's array rounded
+// to 16 bytes (complex elements).
+static int64_t seg_strip_elems(int n, int B) { return ((int64_t)seg_count(n) * B * B + 1) & ~(int64_t)1; }
 // HELM_SWEEP_SEG=0 / 1 forces the plain / segmented chains; unset: segmented where available.
 static int seg_env() {
     const char* e = std::getenv("HELM_SWEEP_SEG");
@@ -388,7 +389,7 @@ extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_
     M->seg = seg_supported(B) && seg_waves_rhs(n) <= seg_max_waves(prec == HELM_C128 ? 0 : 1, B);
     if (M->seg) {
         const int Sg = seg_count(n);
-        const int64_t per_strip = (int64_t)Sg * kSegPH;
+        const int64_t per_strip = seg_strip_elems(n, B);
         if ((rc = M->prop.alloc(esz * (size_t)per_strip * (size_t)(A->nsub - 1)))) return rc;
         std::vector<PropDev> pw;
         for (int u = 0; u + 1 < A->nsub; ++u)
@@ -542,6 +543,8 @@ static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
         if ((rc = M->segch.alloc(sizeof(ChainDev) * sc.size()))) return rc;
         HIPCHK(hipMemcpy(M->segch.p, sc.data(), sizeof(ChainDev) * sc.size(), hipMemcpyHostToDevice));
         M->nsegch = (int)sc.size();
+        const size_t wsb = compute_elem(M->prec) * (size_t)seg_ws_elems(M->nsegch, M->seg_wg);
+        if (M->segws.bytes < wsb && (rc = M->segws.alloc(wsb))) return rc;
         M->kind = seg_env() == 0 ? 0 : 1;
     }
     M->chains_nrhs = nrhs;
@@ -564,7 +567,7 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
         PhaseScope ph(PH_SWEEP_FWD, s);
         const bool ok = M->kind == 1
                             ? launch_chains_seg(B, M->prec, vec_prec, vec_prec, 0, pd, M->segch.as<ChainDev>(), M->nsegch,
-                                                nullptr, io, M->seg_wg, nullptr, s)
+                                                nullptr, io, M->seg_wg, nullptr, M->segws.p, s)
                             : run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd,
                                          M->chains.as<ChainDev>(), M->nchains, nullptr, io, M->spill.p, nullptr, s);
         if (!ok) return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
@@ -580,7 +583,7 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
         PhaseScope ph(PH_SWEEP_BWD, s);
         if (M->kind == 1)
             launch_chains_seg(B, M->prec, vec_prec, vec_prec, 1, pd, M->segch.as<ChainDev>(), M->nsegch, nullptr, io,
-                              M->seg_wg, nullptr, s);
+                              M->seg_wg, nullptr, M->segws.p, s);
         else
             run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
                        nullptr, io, M->spill.p, nullptr, s);
@@ -746,6 +749,7 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
             if ((rc = b->segch.alloc(sizeof(ChainDev) * sc.size()))) return rc;
             HIPCHK(hipMemcpy(b->segch.p, sc.data(), sizeof(ChainDev) * sc.size(), hipMemcpyHostToDevice));
             b->nsegch = (int)sc.size();
+            if ((rc = b->segws.alloc(compute_elem(b->prec) * (size_t)seg_ws_elems(b->nsegch, b->seg_wg)))) return rc;
             std::vector<PropDev> pw;
             for (int p = 0; p < count; ++p) {
                 std::vector<PropDev> one(M[p]->npropw);
@@ -888,7 +892,7 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int3
         PhaseScope ph(PH_SWEEP_FWD, s);
         const bool ok = b->kind == 1
                             ? launch_chains_seg(b->B, b->prec, 0, out_prec, 0, pd, b->segch.as<ChainDev>(), b->nsegch, io,
-                                                none, b->seg_wg, active, s)
+                                                none, b->seg_wg, active, b->segws.p, s)
                             : run_chains(b->waves, b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd,
                                          b->chains.as<ChainDev>(), b->nchains, io, none, b->spill.p, active, s);
         if (!ok) return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
@@ -904,7 +908,7 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int3
         PhaseScope ph(PH_SWEEP_BWD, s);
         if (b->kind == 1)
             launch_chains_seg(b->B, b->prec, 0, out_prec, 1, pd, b->segch.as<ChainDev>(), b->nsegch, io, none, b->seg_wg,
-                              active, s);
+                              active, b->segws.p, s);
         else
             run_chains(b->waves, b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io,
                        none, b->spill.p, active, s);

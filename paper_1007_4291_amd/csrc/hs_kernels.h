@@ -71,9 +71,11 @@ bool launch_chains2(int B, int prec, int in_prec, int out_prec, int phase, int k
 // waves per chain; ChainDev::pad_ = waves per right-hand side (ceil(segments / 4)), nq right-hand
 // sides per workgroup.  io[p].prop must hold the problem's propagators (launch_prop).  Returns false
 // for strip heights without an instance or a workgroup beyond the LDS.
+// ws: workspace of seg_ws_elems(nchains, waves) complex elements of the compute precision.
 bool launch_chains_seg(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
                        const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves,
-                       const int32_t* active, hipStream_t s);
+                       const int32_t* active, void* ws, hipStream_t s);
+int64_t seg_ws_elems(int nchains, int waves);
 bool seg_supported(int B);
 // Largest workgroup (in waves) of the segmented chains that fits the LDS.
 int seg_max_waves(int prec, int B);

@@ -25,9 +25,10 @@
 // the row group that produces those values (B3) is the one that consumes them (F1 of the next strip).
 //
 // The propagators Phi of every segment of every strip are products of stored factor data only and
-// are formed after each factorisation (k_prop), in the factor precision, padded to RP x RP and stored
-// twice: column-major (read by F2) and row-major (read by B2), so both spine products load
-// contiguously.
+// are formed after each factorisation (k_prop), in the factor precision, one row-major B x B block
+// per segment.  F2 reads the blocks, B2 their transposes.  In FP32 the blocks of the strip in hand
+// are staged into LDS while the previous strip's last phase runs, so neither spine waits on global
+// memory; in FP64 the spine loads them from global memory a few segments ahead.
 #include <algorithm>
 
 #include "hs_sweep_util.h"
@@ -113,20 +114,10 @@ __global__ __launch_bounds__(64) void k_prop(const ProbDev* __restrict__ probs, 
         }
         wave_sync();
     }
-    if (rok) {
+    if (seg < S && rok) {
+        HS_GLOBAL CF* out = gptr((CF*)W.out) + (int64_t)seg * BS * BS + r * BS;   // row r of the block
 #pragma unroll
-        for (int c = 0; c < BS; ++c) phb[q][r][c] = ph[c];
-    }
-    wave_sync();
-    if (seg < S) {
-        HS_GLOBAL CF* out = gptr((CF*)W.out) + (int64_t)seg * 2 * RP * RP;
-        const CF zero = mk<TF>(0, 0);
-#pragma unroll
-        for (int k = 0; k < RP; ++k) {
-            // column-major: entry (r, k) at k*RP + r; row-major: entry (k, r) at k*RP + r
-            gst(out + k * RP + r, (rok && k < BS) ? ccast<TF, T>(ph[k < BS ? k : 0]) : zero);
-            gst(out + RP * RP + k * RP + r, (rok && k < BS) ? ccast<TF, T>(phb[q][k < BS ? k : 0][rr]) : zero);
-        }
+        for (int c = 0; c < BS; ++c) gst(out + c, ccast<TF, T>(ph[c]));
     }
 }
 
@@ -138,14 +129,18 @@ template <class T, class TF, int BS> struct SegShape {
     static constexpr int CB = col_stride<TF>(BS) * (int)sizeof(C2<TF>);   // bytes per stored column
     static constexpr int N16 = CB / 16;
     static constexpr int NCR = (N16 + RP - 1) / RP;                      // column chunks per lane
-    // chunks per row group's staged column: 64 bytes of padding shift the row groups of a half wave
+    // chunks per row group's staged column: 32 bytes of padding shift the row groups of a half wave
     // to other LDS banks (the packed-row reads of neighbouring row groups otherwise collide)
-    static constexpr int CSTR = NCR * RP + 4;
+    static constexpr int CSTR = NCR * RP + 2;
     // exchange vectors: LDS only in FP64 (FP32 takes the vector through row broadcasts)
     static constexpr int XZ = sizeof(T) == 8 ? 64 : 0;
-    // LDS bytes per wave: staged columns, exchange vectors, 4 spine vectors per segment slot, layer rows
-    static constexpr int LDS_WAVE = Q * CSTR * 16 + XZ * (int)sizeof(C2<T>) + 4 * Q * RP * (int)sizeof(C2<T>) +
-                                    64 * (int)sizeof(C2<T>);
+    // the strip's segment propagators: LDS only in FP32, up to 4 segments per wave
+    static constexpr int PHL = sizeof(T) == 4 ? Q * BS * BS : 0;
+    // LDS bytes per wave: staged columns, exchange vectors, 2 spine vectors per segment slot, layer
+    // rows, propagators.  (Each spine vector holds the per-segment contributions q / p and the values
+    // entering the segments c / x in turn: their lifetimes are separated by barriers.)
+    static constexpr int LDS_WAVE = Q * CSTR * 16 + XZ * (int)sizeof(C2<T>) + 2 * Q * RP * (int)sizeof(C2<T>) +
+                                    64 * (int)sizeof(C2<T>) + PHL * (int)sizeof(C2<TF>);
 };
 
 // Workgroups of up to 16 waves in FP32 (128 registers per lane) and 8 in FP64.
@@ -154,7 +149,7 @@ template <class T> struct SegWaves { static constexpr int MAX = sizeof(T) == 8 ?
 template <class T, class TF, class TI, class TO, int BS, int MODE>
 __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
                                                  const IoDev* __restrict__ io, IoDev io_val,
-                                                 const int32_t* __restrict__ active) {
+                                                 const int32_t* __restrict__ active, C2<T>* __restrict__ wsp) {
     static_assert(MODE == MODE_FWD || MODE == MODE_BWD, "segmented chains serve the front phases");
     using CT = C2<T>;
     using CF = C2<TF>;
@@ -164,18 +159,19 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     constexpr int PACK = packed_size(BS);
     constexpr int KJ = RP / Q;            // spine: entries of the k-sum per lane
     constexpr int D = 2;                  // column prefetch distance in steps (divides SEG)
-    constexpr int PH = 2 * RP * RP;       // complex entries per stored segment propagator pair
+    constexpr int PH = BS * BS;           // complex entries per stored segment propagator
     static_assert(SEG % D == 0, "ring slots must repeat per phase");
 
     extern __shared__ __align__(16) char smem[];
     const int nw = blockDim.x >> 6;
     chunk16* const colb = (chunk16*)smem;                        // [nw][Q][CSTR]
     CT* const xz = (CT*)(colb + nw * Q * CSTR);                  // [nw][XZ]
-    CT* const qv = xz + nw * SH::XZ;                             // [nw*Q][RP], by segment slot
-    CT* const cv = qv + nw * Q * RP;
-    CT* const pv = cv + nw * Q * RP;
-    CT* const xv = pv + nw * Q * RP;
-    CT* const ylay = xv + nw * Q * RP;                           // [nw*64]: layer rows by column
+    CT* const qv = xz + nw * SH::XZ;                             // [nw*Q][RP], by segment slot: q, then p
+    CT* const cv = qv + nw * Q * RP;                             // carries c, then values x above
+    CT* const pv = qv;
+    CT* const xv = cv;
+    CT* const ylay = cv + nw * Q * RP;                           // [nw*64]: layer rows by column
+    CF* const phl = (CF*)(ylay + nw * 64);                       // [segments][BS*BS] (FP32 only)
 
     const ChainDev ch = chains[blockIdx.x];
     if (ch.nq == 0) return;                                      // padding entry of the table
@@ -241,12 +237,17 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     constexpr bool DPP = sizeof(T) == 4;
     auto rowdot = [&](CT z) __attribute__((always_inline)) -> CT {
         if constexpr (DPP) {
+            // all reads of the row first, so that they are in flight together (the scheduler would
+            // otherwise trade them for register pressure and wait for each in turn)
+            CT lv[BS];
+#pragma unroll
+            for (int k = 0; k < BS; ++k) lv[k] = ccast<T, TF>(cf[loff[k]]);
+            __builtin_amdgcn_sched_barrier(0);
             float a0x = 0.f, a0y = 0.f, a1x = 0.f, a1y = 0.f;
             static_for<BS>([&](auto KC) __attribute__((always_inline)) {
                 constexpr int k = decltype(KC)::value;
-                const CT l = ccast<T, TF>(cf[loff[k]]);
-                if constexpr (k & 1) cfma_rowbcast<k>(a1x, a1y, l.x, l.y, z.x, z.y);
-                else cfma_rowbcast<k>(a0x, a0y, l.x, l.y, z.x, z.y);
+                if constexpr (k & 1) cfma_rowbcast<k>(a1x, a1y, lv[k].x, lv[k].y, z.x, z.y);
+                else cfma_rowbcast<k>(a0x, a0y, lv[k].x, lv[k].y, z.x, z.y);
             });
             return mk<T>(a0x + a1x, a0y + a1y);
         } else {
@@ -299,6 +300,17 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     // register ring: staged column chunks and one input value per step
     chunk16 rk[D][NCR];
     double2 ra[D];
+    CT rg[D];
+    // Workspace: the right-hand side g_t of each step (F1 -> F3), then the forward product w_t
+    // (F3 -> B1, B3), laid out [workgroup][step][thread] so that every access is one coalesced
+    // 8- or 16-byte word per lane; the register file cannot hold 16 steps of it besides the rest.
+    // B1 takes the last D products from registers (wl): their loads would be issued before F3
+    // stores them.
+    const __amdgpu_buffer_rsrc_t wrs = buf_rsrc(gptr(wsp) + (int64_t)blockIdx.x * SEG * blockDim.x,
+                                                (uint32_t)(SEG * blockDim.x * sizeof(CT)));
+    const uint32_t wlane = (uint32_t)(threadIdx.x * sizeof(CT));
+    const uint32_t wstep = (uint32_t)(blockDim.x * sizeof(CT));
+    CT wl[D];
     // PK: 1 = F1, 3 = F3, 5 = B1, 7 = B3; j: step of the segment in LU order
     auto issue = [&](auto PKC, auto JC, auto UC, const Src& s, bool first) __attribute__((always_inline)) {
         constexpr int PK = decltype(PKC)::value, j = decltype(JC)::value, u = decltype(UC)::value;
@@ -313,15 +325,15 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         } else if constexpr (PK == 7) {
             if (MODE == MODE_BWD) ra[u] = ld2(y + (int64_t)(s.row - 1) * n + col - 1);
         }
+        if constexpr (PK == 3 || PK == 7 || (PK == 5 && j < SEG - D)) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
     };
     auto stage = [&](int u) __attribute__((always_inline)) {
 #pragma unroll
         for (int c = 0; c < NCR; ++c) cb[r + c * RP] = rk[u][c];
     };
 
-    CT gw[SEG];
 #pragma unroll
-    for (int j = 0; j < SEG; ++j) gw[j] = mk<T>(0, 0);
+    for (int u = 0; u < D; ++u) { rg[u] = mk<T>(0, 0); wl[u] = mk<T>(0, 0); }
     CT carry = mk<T>(0, 0), xb = mk<T>(0, 0);
 
     // one forward step: F1 (PK 1) builds g_t from the input and the previous layer row, F3 (PK 3)
@@ -343,13 +355,16 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
                 const CT yp = first ? ccast<T, double>(ra[u]) : ylr[col - 1];
                 g = slot ? cmul<T>(colscalar(XCOL_ANEXT), yp) : mk<T>(0, 0);
             }
-            gw[j] = g;
+            buf_st(g, wrs, late(wlane), (uint32_t)j * wstep);
         } else {
-            g = gw[j];
+            g = rg[u];
         }
         const CT w = rowdot(csel<T>(rok, cadd<T>(g, carry), mk<T>(0, 0)));
         const CT ne = cscale<T>(cmul<T>(colscalar(XCOL_E), s.is2), (T)-1);
-        if constexpr (PK == 3) gw[j] = w;
+        if constexpr (PK == 3) {
+            buf_st(w, wrs, late(wlane), (uint32_t)j * wstep);
+            if constexpr (j >= SEG - D) wl[j - (SEG - D)] = w;
+        }
         carry = csel<T>(valid, cmul<T>(ne, w), carry);
         wave_sync();
     };
@@ -362,7 +377,10 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         stage(u);
         wave_sync();
         const CT v = rowdot(csel<T>(rok, cmul<T>(s.is2, xb), mk<T>(0, 0)));
-        const CT xn = cfms<T>(colscalar(XCOL_E), v, gw[j]);
+        CT wj;
+        if constexpr (PK == 5 && j >= SEG - D) wj = wl[j - (SEG - D)];
+        else wj = rg[u];
+        const CT xn = cfms<T>(colscalar(XCOL_E), v, wj);
         xb = csel<T>(valid, xn, xb);
         if constexpr (PK == 7) {
             const int col = colof(s, t);
@@ -375,11 +393,14 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
 
     // Phases.  Every step refills its ring slot with the step D later in the sequence
     // F3(i) B1(i) B3(i) F1(i+1) F3(i+1) ...
-    auto phase_f = [&](auto PKC, const Src& s, bool first, auto NPKC, const Src& ns, bool nfirst) __attribute__((always_inline)) {
+    // hook(position) runs after every step (propagator staging)
+    auto phase_f = [&](auto PKC, const Src& s, bool first, auto NPKC, const Src& ns, bool nfirst, auto&& hook)
+                       __attribute__((always_inline)) {
         const bool full = s.st == 0;
         static_for<SEG>([&](auto JC) __attribute__((always_inline)) {
             constexpr int j = decltype(JC)::value;
             fstep(PKC, JC, s, first, full);
+            hook(JC);
             constexpr int u = j % D;
             if constexpr (j + D < SEG) issue(PKC, std::integral_constant<int, j + D>{}, std::integral_constant<int, u>{}, s, first);
             else {
@@ -391,12 +412,14 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
             }
         });
     };
-    auto phase_b = [&](auto PKC, const Src& s, auto NPKC, const Src& ns, bool nfirst) __attribute__((always_inline)) {
+    auto phase_b = [&](auto PKC, const Src& s, auto NPKC, const Src& ns, bool nfirst, auto&& hook)
+                       __attribute__((always_inline)) {
         const bool full = s.st == 0;
         static_for<SEG>([&](auto KC) __attribute__((always_inline)) {
             constexpr int k = decltype(KC)::value;      // position in the phase
             constexpr int j = SEG - 1 - k;
             bstep(PKC, std::integral_constant<int, j>{}, s, full);
+            hook(KC);
             constexpr int u = k % D;
             if constexpr (k + D < SEG) issue(PKC, std::integral_constant<int, j - D>{}, std::integral_constant<int, u>{}, s, false);
             else {
@@ -414,23 +437,60 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         });
     };
 
+    // Propagators of strip i: PS complex per strip (16-byte aligned), block si at si * PH.
+    const int PS = (S * PH + 1) & ~1;
+    auto phi_strip = [&](int i) __attribute__((always_inline)) -> const HS_GLOBAL CF* {
+        return propbase + (int64_t)(sub0 + strip_t(i <= m ? i : m)) * PS;
+    };
+    // FP32: staging of a strip's blocks into LDS, 16-byte chunk c by live thread c mod T, in eight
+    // rounds spread over the steps of the phases before the strip's first spine (round jj loads chunk
+    // tid + jj*T into a register and stores it to LDS one round later).
+    const int nlive = ch.nq * Wr * 64;         // live waves are the first nq * Wr of the workgroup
+    const int npc = PS * (int)sizeof(CF) / 16;
+    chunk16 phr = {0, 0, 0, 0};
+    const HS_GLOBAL chunk16* phsrc = nullptr;
+    auto phi_round = [&](int jj) __attribute__((always_inline)) {
+        if constexpr (sizeof(T) == 4) {
+            if (jj > 0) {
+                const int c = (int)threadIdx.x + (jj - 1) * nlive;
+                if (c < npc) ((chunk16*)phl)[c] = phr;
+            }
+            if (jj < 8) {
+                const int c = (int)threadIdx.x + jj * nlive;
+                phr = phsrc[c < npc ? c : npc - 1];
+            }
+        }
+    };
+    auto phi_begin = [&](int i) __attribute__((always_inline)) {
+        phsrc = (const HS_GLOBAL chunk16*)phi_strip(i);
+    };
+
     // Spines: one wave per right-hand side; lane (q, r) sums k = jj*Q + q, the row groups are combined
-    // with cross-row sums.  Propagators of later segments are prefetched DS steps ahead.
+    // with cross-row sums.  F2 takes row rr of each block, B2 column rr.  FP64 loads the blocks from
+    // global memory DS segments ahead.
     constexpr int DS = 2;
     auto spine_run = [&](int i, bool fwd) __attribute__((always_inline)) {
-        const Src s = src_of(i);
-        const HS_GLOBAL CF* const ph = propbase + (int64_t)(sub0 + s.st) * S * PH + (fwd ? 0 : RP * RP);
-        CT* const vin = fwd ? qv : pv;     // segment contributions
-        CT* const vout = fwd ? cv : xv;    // value entering each segment
+        const int cd = strip_dir(i <= m ? i : m);
+        const HS_GLOBAL CF* const gph = phi_strip(i);
+        CT* const vin = qv;     // segment contributions q (F2) / p (B2)
+        CT* const vout = cv;    // values entering the segments: carries c (F2) / x above (B2)
         auto sidx = [&](int k) __attribute__((always_inline)) -> int {
             const int kc = k < S ? k : S - 1;
-            return (fwd == (s.cd > 0)) ? kc : S - 1 - kc;
+            return (fwd == (cd > 0)) ? kc : S - 1 - kc;
         };
         CT pr[DS][KJ];
         auto pload = [&](int u, int k) __attribute__((always_inline)) {
-            const HS_GLOBAL CF* p = ph + (int64_t)sidx(k) * PH + q * RP + r;
+            const int base = sidx(k) * PH;
 #pragma unroll
-            for (int jj = 0; jj < KJ; ++jj) pr[u][jj] = ccast<T, TF>(gld(p + jj * Q * RP));
+            for (int jj = 0; jj < KJ; ++jj) {
+                const int kk = jj * Q + q;
+                const int kc = kk < BS ? kk : BS - 1;
+                const int e = base + (fwd ? rr * BS + kc : kc * BS + rr);
+                CT v;
+                if constexpr (sizeof(T) == 4) v = ccast<T, TF>(phl[e]);
+                else v = ccast<T, TF>(gld(gph + e));
+                pr[u][jj] = csel<T>(rok && kk < BS, v, mk<T>(0, 0));
+            }
         };
         static_for<DS>([&](auto UC) __attribute__((always_inline)) { pload(decltype(UC)::value, decltype(UC)::value); });
         CT v = mk<T>(0, 0);
@@ -458,29 +518,46 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         }
     };
 
-    // prologue: F1 of strip 0, its spine
+    auto no_hook = [](auto) __attribute__((always_inline)) {};
+    // prologue: F1 of strip 0 (staging strip 0's propagators every second step), its spine
     Src sc = src_of(0), sn = src_of(1);
+    phi_begin(0);
     prime(std::integral_constant<int, 1>{}, sc, true);
-    phase_f(std::integral_constant<int, 1>{}, sc, true, std::integral_constant<int, 3>{}, sc, false);
+    phase_f(std::integral_constant<int, 1>{}, sc, true, std::integral_constant<int, 3>{}, sc, false,
+            [&](auto KC) __attribute__((always_inline)) {
+                if constexpr (decltype(KC)::value % 2 == 0) phi_round(decltype(KC)::value / 2);
+            });
+    phi_round(8);
     qv[sl * RP + r] = csel<T>(rok, carry, mk<T>(0, 0));
     wg_barrier();
     if (spine) spine_run(0, true);
     wg_barrier();
     for (int i = 0; i <= m; ++i) {
         carry = cv[sl * RP + r];
-        phase_f(std::integral_constant<int, 3>{}, sc, false, std::integral_constant<int, 5>{}, sc, false);
+        phase_f(std::integral_constant<int, 3>{}, sc, false, std::integral_constant<int, 5>{}, sc, false, no_hook);
         carry = mk<T>(0, 0);
         xb = mk<T>(0, 0);
-        phase_b(std::integral_constant<int, 5>{}, sc, std::integral_constant<int, 7>{}, sc, false);
+        phase_b(std::integral_constant<int, 5>{}, sc, std::integral_constant<int, 7>{}, sc, false, no_hook);
         pv[sl * RP + r] = csel<T>(rok, xb, mk<T>(0, 0));
         wg_barrier();
         if (spine) spine_run(i, false);
         wg_barrier();
+        // strip i's propagators are no longer read: stage strip i + 1's during B3(i) and F1(i + 1)
+        const bool more = i < m;
+        if (more) phi_begin(i + 1);
         xb = xv[sl * RP + r];
-        phase_b(std::integral_constant<int, 7>{}, sc, std::integral_constant<int, 1>{}, sn, false);
-        if (i < m) {
+        phase_b(std::integral_constant<int, 7>{}, sc, std::integral_constant<int, 1>{}, sn, false,
+                [&](auto KC) __attribute__((always_inline)) {
+                    if constexpr (decltype(KC)::value % 4 == 0)
+                        if (more) phi_round(decltype(KC)::value / 4);
+                });
+        if (more) {
             carry = mk<T>(0, 0);
-            phase_f(std::integral_constant<int, 1>{}, sn, false, std::integral_constant<int, 3>{}, sn, false);
+            phase_f(std::integral_constant<int, 1>{}, sn, false, std::integral_constant<int, 3>{}, sn, false,
+                    [&](auto KC) __attribute__((always_inline)) {
+                        if constexpr (decltype(KC)::value % 4 == 0) phi_round(4 + decltype(KC)::value / 4);
+                    });
+            phi_round(8);
             qv[sl * RP + r] = csel<T>(rok, carry, mk<T>(0, 0));
             wg_barrier();
             if (spine) spine_run(i + 1, true);
@@ -512,19 +589,20 @@ int seg_max_waves(int prec, int B) { return prec == 0 ? seg_waves_typed<double, 
 
 template <class T, class TF, class TI, class TO, int BV, int MODE>
 static bool segp_launch(const ProbDev* probs, const ChainDev* chains, int nb, const IoDev* io, IoDev iov, int waves,
-                        const int32_t* act, hipStream_t s) {
+                        const int32_t* act, void* ws, hipStream_t s) {
     const size_t lds = (size_t)SegShape<T, TF, BV>::LDS_WAVE * waves;
     if (lds > 160 * 1024) return false;
-    hipLaunchKernelGGL((k_sweepP<T, TF, TI, TO, BV, MODE>), dim3(nb), dim3(64 * waves), lds, s, probs, chains, io, iov, act);
+    hipLaunchKernelGGL((k_sweepP<T, TF, TI, TO, BV, MODE>), dim3(nb), dim3(64 * waves), lds, s, probs, chains, io, iov, act,
+                       (C2<T>*)ws);
     return true;
 }
 
 template <class T, class TF, class TI, class TO, int MODE>
 static bool segp_typed(int bs, const ProbDev* probs, const ChainDev* chains, int nb, const IoDev* io, IoDev iov,
-                       int waves, const int32_t* act, hipStream_t s) {
+                       int waves, const int32_t* act, void* ws, hipStream_t s) {
     switch (bs) {
 #define HS_CASE(BV) \
-    case BV: return segp_launch<T, TF, TI, TO, BV, MODE>(probs, chains, nb, io, iov, waves, act, s);
+    case BV: return segp_launch<T, TF, TI, TO, BV, MODE>(probs, chains, nb, io, iov, waves, act, ws, s);
         HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13)
 #undef HS_CASE
         default: return false;
@@ -533,29 +611,33 @@ static bool segp_typed(int bs, const ProbDev* probs, const ChainDev* chains, int
 
 template <int MODE>
 static bool segp_prec(int bs, int prec, int in_prec, int out_prec, const ProbDev* probs, const ChainDev* chains, int nb,
-                      const IoDev* io, IoDev iov, int waves, const int32_t* act, hipStream_t s) {
+                      const IoDev* io, IoDev iov, int waves, const int32_t* act, void* ws, hipStream_t s) {
     if (prec == 0) {
         if (in_prec == 0 && out_prec == 0)
-            return segp_typed<double, double, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, s);
+            return segp_typed<double, double, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, s);
         return false;
     }
     if (in_prec == 0 && out_prec == 0)
-        return segp_typed<float, float, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, s);
+        return segp_typed<float, float, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, s);
     if (in_prec == 0 && out_prec == 1)
-        return segp_typed<float, float, double2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, s);
+        return segp_typed<float, float, double2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, s);
     if (in_prec == 1 && out_prec == 1)
-        return segp_typed<float, float, float2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, s);
+        return segp_typed<float, float, float2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, s);
     return false;
 }
 
 bool launch_chains_seg(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
                        const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves,
-                       const int32_t* active, hipStream_t s) {
+                       const int32_t* active, void* ws, hipStream_t s) {
     if (nchains <= 0) return true;
     if (waves < 1 || waves > seg_max_waves(prec, B)) return false;
-    return phase == 0 ? segp_prec<MODE_FWD>(B, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, waves, active, s)
-                      : segp_prec<MODE_BWD>(B, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, waves, active, s);
+    return phase == 0 ? segp_prec<MODE_FWD>(B, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, waves, active,
+                                            ws, s)
+                      : segp_prec<MODE_BWD>(B, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, waves, active,
+                                            ws, s);
 }
+
+int64_t seg_ws_elems(int nchains, int waves) { return (int64_t)nchains * SEG * 64 * waves; }
 
 template <class T, class TF>
 static bool prop_typed(int bs, const ProbDev* probs, const PropDev* work, int nwork, hipStream_t s) {
