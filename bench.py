@@ -131,15 +131,17 @@ def sweep_bytes_flops(probs, B, fac_bytes, vin, vout):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_chains_batched96_c64_traffic.json")
 
 
-def measured_traffic(workload, prec_name):
+def measured_traffic(workload, prec_name, kind):
     """HBM bytes per chain launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by
-    the copy-kernel calibration), or None when they do not describe this workload or when the kernel
-    sources have changed since the counters were taken."""
+    the copy-kernel calibration), or None when they do not describe this workload and chain kernel or
+    when the kernel sources have changed since the counters were taken."""
     import hashlib
     if workload != "batched" or prec_name != "c64" or not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         tr = json.load(fh)
+    if tr.get("chain_kind") != kind:
+        return None
     h = hashlib.sha256()
     for f in tr.get("source_files", []):
         with open(os.path.join(ROOT, f), "rb") as fh:
@@ -208,10 +210,13 @@ def main():
     avg_ms = (ms_f + ms_b) / max(1, n_f + n_b)
     bytes_per_launch = (b0 + b1) / 2
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(a.workload, a.prec)
+    kind = "segmented" if schedule.get("segmented") else "plain"
+    traffic = measured_traffic(a.workload, a.prec, kind)
+    kname = ("k_sweepP (segmented chains)" if kind == "segmented"
+             else f"k_sweep{'2' if schedule.get('waves') == 2 else ''} (chains)") + " forward/backward launches"
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": int(traffic) if traffic else None,
-            "kernel": "k_sweep forward/backward chain launches", "avg_launch_ms": round(avg_ms, 4),
+            "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
             "launches": n_f + n_b, "algorithmic_bytes_per_launch": int(bytes_per_launch),
             "tflops": round(fl / (avg_ms * 1e-3) / 1e12, 4)}
 
