@@ -311,10 +311,12 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     const uint32_t wlane = (uint32_t)(threadIdx.x * sizeof(CT));
     const uint32_t wstep = (uint32_t)(blockDim.x * sizeof(CT));
     CT wl[D];
-    // PK: 1 = F1, 3 = F3, 5 = B1, 7 = B3; j: step of the segment in LU order
-    auto issue = [&](auto PKC, auto JC, auto UC, const Src& s, bool first) __attribute__((always_inline)) {
-        constexpr int PK = decltype(PKC)::value, j = decltype(JC)::value, u = decltype(UC)::value;
-        const uint32_t vo = late(s.vb) + (uint32_t)(j * CB);
+    // PK: 1 = F1, 3 = F3, 5 = B1, 7 = B3; j: step of the segment in LU order (runtime), u: ring slot.
+    // The phases are loops over groups of D steps (only the ring slot is a compile-time index), which
+    // keeps the kernel's code within the instruction cache; fully unrolled it was 84 KB.
+    auto issue = [&](auto PKC, int j, auto UC, const Src& s, bool first) __attribute__((always_inline)) {
+        constexpr int PK = decltype(PKC)::value, u = decltype(UC)::value;
+        const uint32_t vo = late(s.vb) + (uint32_t)j * (uint32_t)CB;
 #pragma unroll
         for (int c = 0; c < NCR; ++c) rk[u][c] = buf_ld16(s.col, vo + (uint32_t)(c * RP * 16), 0);
         const int t = late(s.tb) + j;
@@ -325,7 +327,11 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         } else if constexpr (PK == 7) {
             if (MODE == MODE_BWD) ra[u] = ld2(y + (int64_t)(s.row - 1) * n + col - 1);
         }
-        if constexpr (PK == 3 || PK == 7 || (PK == 5 && j < SEG - D)) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
+        // B1 takes the last D forward products from registers (their loads would precede the stores)
+        if constexpr (PK == 3 || PK == 7) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
+        else if constexpr (PK == 5) {
+            if (j < SEG - D) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
+        }
     };
     auto stage = [&](int u) __attribute__((always_inline)) {
 #pragma unroll
@@ -336,10 +342,10 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     for (int u = 0; u < D; ++u) { rg[u] = mk<T>(0, 0); wl[u] = mk<T>(0, 0); }
     CT carry = mk<T>(0, 0), xb = mk<T>(0, 0);
 
-    // one forward step: F1 (PK 1) builds g_t from the input and the previous layer row, F3 (PK 3)
-    // takes it from registers and leaves w_t there
-    auto fstep = [&](auto PKC, auto JC, const Src& s, bool first, bool full) __attribute__((always_inline)) {
-        constexpr int PK = decltype(PKC)::value, j = decltype(JC)::value, u = j % D;
+    // one forward step: F1 (PK 1) builds g_t from the input and the previous layer row and stores it,
+    // F3 (PK 3) loads it back and stores w_t
+    auto fstep = [&](auto PKC, int j, auto UC, const Src& s, bool first, bool full) __attribute__((always_inline)) {
+        constexpr int PK = decltype(PKC)::value, u = decltype(UC)::value;
         const int t = late(s.tb) + j;
         const bool valid = segok && t >= 0 && t < n;
         stage(u);
@@ -363,23 +369,23 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const CT ne = cscale<T>(cmul<T>(colscalar(XCOL_E), s.is2), (T)-1);
         if constexpr (PK == 3) {
             buf_st(w, wrs, late(wlane), (uint32_t)j * wstep);
-            if constexpr (j >= SEG - D) wl[j - (SEG - D)] = w;
+            if (j >= SEG - D) wl[u] = w;      // j - (SEG - D) == u
         }
         carry = csel<T>(valid, cmul<T>(ne, w), carry);
         wave_sync();
     };
     // one backward step: B1 (PK 5) from a zero value above, B3 (PK 7) writes the strip's outputs
-    auto bstep = [&](auto PKC, auto JC, const Src& s, bool full) __attribute__((always_inline)) {
-        constexpr int PK = decltype(PKC)::value, j = decltype(JC)::value;
-        constexpr int u = (SEG - 1 - j) % D;
+    auto bstep = [&](auto PKC, int j, auto UC, const Src& s, bool full) __attribute__((always_inline)) {
+        constexpr int PK = decltype(PKC)::value, u = decltype(UC)::value;
         const int t = late(s.tb) + j;
         const bool valid = segok && t >= 0 && t < n;
         stage(u);
         wave_sync();
         const CT v = rowdot(csel<T>(rok, cmul<T>(s.is2, xb), mk<T>(0, 0)));
-        CT wj;
-        if constexpr (PK == 5 && j >= SEG - D) wj = wl[j - (SEG - D)];
-        else wj = rg[u];
+        CT wj = rg[u];
+        if constexpr (PK == 5) {
+            if (j >= SEG - D) wj = wl[D - 1 - u];   // j - (SEG - D) == D - 1 - u
+        }
         const CT xn = cfms<T>(colscalar(XCOL_E), v, wj);
         xb = csel<T>(valid, xn, xb);
         if constexpr (PK == 7) {
@@ -392,48 +398,44 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     };
 
     // Phases.  Every step refills its ring slot with the step D later in the sequence
-    // F3(i) B1(i) B3(i) F1(i+1) F3(i+1) ...
-    // hook(position) runs after every step (propagator staging)
+    // F3(i) B1(i) B3(i) F1(i+1) F3(i+1) ...; the last group of a phase prefetches the next phase's
+    // first group (a backward phase starts at j = SEG-1, a forward one at 0).
+    // hook(position) runs after every step (propagator staging).
+    constexpr int NG = SEG / D;
     auto phase_f = [&](auto PKC, const Src& s, bool first, auto NPKC, const Src& ns, bool nfirst, auto&& hook)
                        __attribute__((always_inline)) {
+        constexpr int NPK = decltype(NPKC)::value;
         const bool full = s.st == 0;
-        static_for<SEG>([&](auto JC) __attribute__((always_inline)) {
-            constexpr int j = decltype(JC)::value;
-            fstep(PKC, JC, s, first, full);
-            hook(JC);
-            constexpr int u = j % D;
-            if constexpr (j + D < SEG) issue(PKC, std::integral_constant<int, j + D>{}, std::integral_constant<int, u>{}, s, first);
-            else {
-                // next phase: a backward phase (F3 -> B1) starts at j = SEG-1; a forward one (F1 -> F3) at 0
-                constexpr int NPK = decltype(NPKC)::value;
-                constexpr int k = j + D - SEG;
-                constexpr int nj = (NPK == 5 || NPK == 7) ? SEG - 1 - k : k;
-                issue(NPKC, std::integral_constant<int, nj>{}, std::integral_constant<int, u>{}, ns, nfirst);
-            }
-        });
+        for (int gi = 0; gi < NG; ++gi) {
+            static_for<D>([&](auto UC) __attribute__((always_inline)) {
+                constexpr int u = decltype(UC)::value;
+                const int j = gi * D + u;
+                fstep(PKC, j, UC, s, first, full);
+                hook(j);
+                if (gi + 1 < NG) issue(PKC, j + D, UC, s, first);
+                else issue(NPKC, (NPK == 5 || NPK == 7) ? SEG - 1 - u : u, UC, ns, nfirst);
+            });
+        }
     };
     auto phase_b = [&](auto PKC, const Src& s, auto NPKC, const Src& ns, bool nfirst, auto&& hook)
                        __attribute__((always_inline)) {
+        constexpr int NPK = decltype(NPKC)::value;
         const bool full = s.st == 0;
-        static_for<SEG>([&](auto KC) __attribute__((always_inline)) {
-            constexpr int k = decltype(KC)::value;      // position in the phase
-            constexpr int j = SEG - 1 - k;
-            bstep(PKC, std::integral_constant<int, j>{}, s, full);
-            hook(KC);
-            constexpr int u = k % D;
-            if constexpr (k + D < SEG) issue(PKC, std::integral_constant<int, j - D>{}, std::integral_constant<int, u>{}, s, false);
-            else {
-                constexpr int NPK = decltype(NPKC)::value;
-                constexpr int kk = k + D - SEG;
-                constexpr int nj = (NPK == 5 || NPK == 7) ? SEG - 1 - kk : kk;
-                issue(NPKC, std::integral_constant<int, nj>{}, std::integral_constant<int, u>{}, ns, nfirst);
-            }
-        });
+        for (int gi = 0; gi < NG; ++gi) {
+            static_for<D>([&](auto UC) __attribute__((always_inline)) {
+                constexpr int u = decltype(UC)::value;
+                const int k = gi * D + u;                  // position in the phase
+                const int j = SEG - 1 - k;
+                bstep(PKC, j, UC, s, full);
+                hook(k);
+                if (gi + 1 < NG) issue(PKC, j - D, UC, s, false);
+                else issue(NPKC, (NPK == 5 || NPK == 7) ? SEG - 1 - u : u, UC, ns, nfirst);
+            });
+        }
     };
     auto prime = [&](auto PKC, const Src& s, bool first) __attribute__((always_inline)) {
         static_for<D>([&](auto UC) __attribute__((always_inline)) {
-            constexpr int u = decltype(UC)::value;
-            issue(PKC, std::integral_constant<int, u>{}, UC, s, first);
+            issue(PKC, (int)decltype(UC)::value, UC, s, first);
         });
     };
 
@@ -518,14 +520,14 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         }
     };
 
-    auto no_hook = [](auto) __attribute__((always_inline)) {};
+    auto no_hook = [](int) __attribute__((always_inline)) {};
     // prologue: F1 of strip 0 (staging strip 0's propagators every second step), its spine
     Src sc = src_of(0), sn = src_of(1);
     phi_begin(0);
     prime(std::integral_constant<int, 1>{}, sc, true);
     phase_f(std::integral_constant<int, 1>{}, sc, true, std::integral_constant<int, 3>{}, sc, false,
-            [&](auto KC) __attribute__((always_inline)) {
-                if constexpr (decltype(KC)::value % 2 == 0) phi_round(decltype(KC)::value / 2);
+            [&](int pos) __attribute__((always_inline)) {
+                if ((pos & 1) == 0) phi_round(pos >> 1);
             });
     phi_round(8);
     qv[sl * RP + r] = csel<T>(rok, carry, mk<T>(0, 0));
@@ -547,15 +549,14 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         if (more) phi_begin(i + 1);
         xb = xv[sl * RP + r];
         phase_b(std::integral_constant<int, 7>{}, sc, std::integral_constant<int, 1>{}, sn, false,
-                [&](auto KC) __attribute__((always_inline)) {
-                    if constexpr (decltype(KC)::value % 4 == 0)
-                        if (more) phi_round(decltype(KC)::value / 4);
+                [&](int pos) __attribute__((always_inline)) {
+                    if (more && (pos & 3) == 0) phi_round(pos >> 2);
                 });
         if (more) {
             carry = mk<T>(0, 0);
             phase_f(std::integral_constant<int, 1>{}, sn, false, std::integral_constant<int, 3>{}, sn, false,
-                    [&](auto KC) __attribute__((always_inline)) {
-                        if constexpr (decltype(KC)::value % 4 == 0) phi_round(4 + decltype(KC)::value / 4);
+                    [&](int pos) __attribute__((always_inline)) {
+                        if ((pos & 3) == 0) phi_round(4 + (pos >> 2));
                     });
             phi_round(8);
             qv[sl * RP + r] = csel<T>(rok, carry, mk<T>(0, 0));
