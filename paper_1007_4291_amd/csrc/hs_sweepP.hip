@@ -263,7 +263,6 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
             return cadd<T>(acc0, acc1);
         }
     };
-    auto colscalar = [&](int which) __attribute__((always_inline)) -> CT { return ccast<T, TF>(cf[PACK + which]); };
 
     // Per-strip sources: the strip's stored columns (buffer resource: out-of-range offsets read
     // zeros), this row group's first LU step, column direction, input / output rows.
@@ -311,6 +310,23 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     const uint32_t wlane = (uint32_t)(threadIdx.x * sizeof(CT));
     const uint32_t wstep = (uint32_t)(blockDim.x * sizeof(CT));
     CT wl[D];
+    // A column's coupling scalar (E, or the layer-row couplings), taken from the prefetch ring of the
+    // lane that loaded it (a DPP row broadcast instead of an LDS read): entry PACK + W of the column
+    // lies in chunk (PACK + W) * sizeof(CF) / 16, which lane chunk % RP holds as ring chunk chunk / RP.
+    auto ringscalar = [&](auto WC, int u) __attribute__((always_inline)) -> CT {
+        constexpr int W = decltype(WC)::value;
+        constexpr int BYTE = (PACK + W) * (int)sizeof(CF);
+        constexpr int CH = BYTE / 16, LN = CH % RP, C = CH / RP, DW = (BYTE % 16) / 4;
+        const chunk16 v = rk[u][C];
+        uint32_t d[sizeof(CF) / 4];
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(CF) / 4); ++i)
+            d[i] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[DW + i], 0x150 + LN, 0xF, 0xF, false);
+        CF out;
+        if constexpr (sizeof(CF) == 8) out = make_float2(__uint_as_float(d[0]), __uint_as_float(d[1]));
+        else out = make_double2(__hiloint2double((int)d[1], (int)d[0]), __hiloint2double((int)d[3], (int)d[2]));
+        return ccast<T, TF>(out);
+    };
     // PK: 1 = F1, 3 = F3, 5 = B1, 7 = B3; j: step of the segment in LU order (runtime), u: ring slot.
     // The phases are loops over groups of D steps (only the ring slot is a compile-time index), which
     // keeps the kernel's code within the instruction cache; fully unrolled it was 84 KB.
@@ -350,23 +366,27 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const bool valid = segok && t >= 0 && t < n;
         stage(u);
         wave_sync();
+        // cross-lane reads first, with every lane active (a DPP source lane outside the exec mask
+        // reads as zero)
+        const CT sE = ringscalar(std::integral_constant<int, XCOL_E>{}, u);
         CT g;
         if constexpr (PK == 1) {
+            const CT sL = ringscalar(std::integral_constant<int, MODE == MODE_FWD ? XCOL_APREV : XCOL_ANEXT>{}, u);
             const int col = colof(s, t);
             if (MODE == MODE_FWD) {
                 CT gv = ccast<T, double>(ra[u]);
-                if (!full) gv = csub<T>(gv, cmul<T>(colscalar(XCOL_APREV), ylr[col - 1]));
+                if (!full) gv = csub<T>(gv, cmul<T>(sL, ylr[col - 1]));
                 g = (full ? rok : slot) ? gv : mk<T>(0, 0);
             } else {
                 const CT yp = first ? ccast<T, double>(ra[u]) : ylr[col - 1];
-                g = slot ? cmul<T>(colscalar(XCOL_ANEXT), yp) : mk<T>(0, 0);
+                g = slot ? cmul<T>(sL, yp) : mk<T>(0, 0);
             }
             buf_st(g, wrs, late(wlane), (uint32_t)j * wstep);
         } else {
             g = rg[u];
         }
         const CT w = rowdot(csel<T>(rok, cadd<T>(g, carry), mk<T>(0, 0)));
-        const CT ne = cscale<T>(cmul<T>(colscalar(XCOL_E), s.is2), (T)-1);
+        const CT ne = cscale<T>(cmul<T>(sE, s.is2), (T)-1);
         if constexpr (PK == 3) {
             buf_st(w, wrs, late(wlane), (uint32_t)j * wstep);
             if (j >= SEG - D) wl[u] = w;      // j - (SEG - D) == u
@@ -381,12 +401,13 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const bool valid = segok && t >= 0 && t < n;
         stage(u);
         wave_sync();
+        const CT sE = ringscalar(std::integral_constant<int, XCOL_E>{}, u);
         const CT v = rowdot(csel<T>(rok, cmul<T>(s.is2, xb), mk<T>(0, 0)));
         CT wj = rg[u];
         if constexpr (PK == 5) {
             if (j >= SEG - D) wj = wl[D - 1 - u];   // j - (SEG - D) == D - 1 - u
         }
-        const CT xn = cfms<T>(colscalar(XCOL_E), v, wj);
+        const CT xn = cfms<T>(sE, v, wj);
         xb = csel<T>(valid, xn, xb);
         if constexpr (PK == 7) {
             const int col = colof(s, t);
