@@ -99,7 +99,11 @@ int helm_matvec(helm_problem_t A, const void* x, int32_t x_prec, void* y, int32_
  * n/2+1 (even n).  Each strip, in the x2-first ordering of Section 2.2, is block tridiagonal over the
  * n columns with B x B (middle: 2B-1) blocks D_i and diagonal couplings E_i; the block LU
  * Lambda_1 = D_1, Lambda_i = D_i - E_i Lambda_{i-1}^{-1} E_i is computed in FP64 and the complex
- * symmetric Lambda_i^{-1} stored packed (upper triangle) in `prec`.
+ * symmetric Lambda_i^{-1} stored packed (upper triangle) in `prec`.  Where the segmented sweep
+ * applies (B <= 13 and n <= 1024, or n <= 512 with complex128 factors) the propagator of every
+ * 16-column segment of every front strip (the product of its steps' maps, a B x B block) is formed
+ * from the stored factors as well; they serve only to apply the same M_alpha with a shorter
+ * sequential path.
  * Returns HELM_ESINGULAR if a block has a zero or non-finite pivot.  Synchronises `stream`. */
 int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_factors_t* out);
 
@@ -159,7 +163,7 @@ int sweep_apply_batch(helm_batch_t b, const void* const* f, void* const* u, void
  * batch's own first Krylov block, zeroed) for every candidate schedule and keeps the fastest for all
  * later solves and applications of the batch.  Candidates: the segmented chains (every strip solve
  * split into 16-column segments joined by a short sequential pass over segment propagators; strip
- * heights <= 16 and n <= 1024, or 832 for complex128 factors), and the plain chains with two waves
+ * heights <= 13 and n <= 1024, or 512 for complex128 factors), and the plain chains with two waves
  * per chain (backward and forward pass of a strip pair on separate waves, heights <= 17) or one,
  * each with the number of row groups every right-hand side's block products are split over (1, 2,
  * 4, ... dividing the row groups of a wave).  Each is run `reps` times after one warm-up.  Results
@@ -173,7 +177,8 @@ int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32_t* ksplit,
 
 /* a2 for the whole batch (Algorithm 3 for every problem): recompute the factors of every member
  * from its problem's current tables, all height-B strips of all problems in one launch and the
- * middle strips in a second one that overlaps it.  Equivalent to sweep_refactor on each member;
+ * middle strips in a second one that overlaps it, then (segmented sweep) the segment propagators of
+ * all problems in a third.  Equivalent to sweep_refactor on each member;
  * allocates nothing.  Returns HELM_ESINGULAR naming the first problem with a zero or non-finite
  * pivot.  Synchronises `stream`. */
 int sweep_refactor_batch(helm_batch_t b, void* stream);

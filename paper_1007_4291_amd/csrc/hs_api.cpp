@@ -310,7 +310,7 @@ static int factor_into(sweep_factors_t M, hipStream_t s) {
     const ProbDev* pd = A->pd.as<ProbDev>();
     (void)n;
     {
-        PhaseScope ph(PH_FACTOR, s, 2);
+        PhaseScope ph(PH_FACTOR, s, M->seg ? 3 : 2);
         if (!launch_factor(B, M->prec, pd, M->subs.as<SubDev>(), A->nsub - 1, M->status.as<int>(), s))
             return fail(HELM_EINVAL, "no factor kernel for B=%d", B);
         LAUNCHCHK();
@@ -824,7 +824,7 @@ extern "C" int sweep_refactor_batch(helm_batch_t b, void* stream) {
     const int B = b->B;
     HIPCHK(hipMemsetAsync(b->fstatus.p, 0, sizeof(int) * b->count, s));
     {
-        PhaseScope ph(PH_FACTOR, s, 2);
+        PhaseScope ph(PH_FACTOR, s, b->seg ? 3 : 2);
         // middles (few, long) on the side stream, overlapping the many height-B strips
         HIPCHK(hipEventRecord(b->ev_fork, s));
         HIPCHK(hipStreamWaitEvent(b->side, b->ev_fork, 0));

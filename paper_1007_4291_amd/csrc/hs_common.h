@@ -140,7 +140,7 @@ struct ChainDev {
     int32_t front;      // 0: upward front (F, B+1, ..., c-1); 1: downward front (E, n-B, ..., c+1)
     int32_t rhs0, nq;   // first right-hand side and count (<= lanes / padded rows)
     int32_t sys0;       // system index of the first right-hand side (batch order, problem-major)
-    int32_t pad_;
+    int32_t wrhs;       // segmented chains: waves per right-hand side (plain chains: unused)
     int64_t spill_off;  // offset of this chain's workspace (complex elements)
 };
 
@@ -170,7 +170,7 @@ struct PropDev {
     int32_t seg0;
     const void* fac;        // first stored column of the strip
     const double2* ris2;
-    void* out;              // the strip's propagators: [segment][column-major, row-major][RP * RP]
+    void* out;              // the strip's propagators: [segment][row-major BS x BS block]
 };
 
 __host__ __device__ constexpr int packed_size(int bs) { return bs * (bs + 1) / 2; }

@@ -68,7 +68,7 @@ bool launch_chains2(int B, int prec, int in_prec, int out_prec, int phase, int k
                     const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, void* spill,
                     const int32_t* active, hipStream_t s);
 // Segmented chains (strip solves partitioned into SEG-column segments): one workgroup of `waves`
-// waves per chain; ChainDev::pad_ = waves per right-hand side (ceil(segments / 4)), nq right-hand
+// waves per chain; ChainDev::wrhs = waves per right-hand side (ceil(segments / 4)), nq right-hand
 // sides per workgroup.  io[p].prop must hold the problem's propagators (launch_prop).  Returns false
 // for strip heights without an instance or a workgroup beyond the LDS.
 // ws: workspace of seg_ws_elems(nchains, waves) complex elements of the compute precision.

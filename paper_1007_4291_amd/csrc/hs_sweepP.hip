@@ -181,7 +181,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     const int L = ch.front == 0 ? P.L_lo : P.L_up;
     const int m = L;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane % RP, q = lane / RP;
-    const int Wr = ch.pad_;                    // waves per right-hand side
+    const int Wr = ch.wrhs;                    // waves per right-hand side
     const int rl = wv / Wr, wr = wv - rl * Wr;
     const bool live = rl < ch.nq;              // wave-uniform
     if (!live) {
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         return s.cd > 0 ? tc + 1 : n - tc;
     };
 
-    // register ring: staged column chunks and one input value per step
+    // register ring: the column chunks, one input value and one workspace value per step
     chunk16 rk[D][NCR];
     double2 ra[D];
     CT rg[D];
