@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--workload", default="batched", choices=["batched", "lens255", "grf1023", "const63"])
     ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 comparison (0: skip)")
+    ap.add_argument("--graph-steps", type=int, default=1,
+                    help="timed steps with each restart cycle replayed as a captured hipGraph (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-size", type=int, default=32, help="problems per size in the batched workload")
     return ap.parse_args()
@@ -233,6 +235,16 @@ def main():
            "phase_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in ph.items()},
            "sweep_schedule": schedule,
            "roofline": roof}
+
+    if a.graph_steps > 0:
+        # the same step with every FGMRES restart cycle one graph replay (captured in the warm-up step)
+        run.batch.use_graph(True)
+        tg, _ = timed(run, torch, a.graph_steps, 1)
+        same = all(bool((u1 == u2).all()) for u1, u2 in zip(run.u, u_main)) and run.last.iters == res.iters
+        run.batch.use_graph(False)
+        out["graph"] = {"value": tot_unknowns / tg, "ms_per_step": tg * 1e3, "steps": a.graph_steps,
+                        "equals_eager": same}
+        print(f"[bench] graph form: {tg * 1e3:.1f} ms/step (equal to eager: {same})", file=sys.stderr, flush=True)
 
     if a.fp64_steps > 0 and prec != hs.HELM_C128:
         del run

@@ -155,6 +155,19 @@ int helm_batch_create(const helm_problem_t* A, const sweep_factors_t* M, const i
 int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* const* u, double tol,
                        int32_t maxit, int32_t* iters, double* relres, void* stream);
 
+/* a7 -- Graph form of fgmres_solve_batch (the solver of Section 2.3 with few host round trips).
+ * on != 0: later solves of the batch run every restart cycle as replays of hipGraphs captured at
+ * the first such solve -- the Arnoldi steps with the preconditioner in chunks of 4, then the update,
+ * the new residual and the convergence flags -- with the per-system bookkeeping (iteration counts,
+ * leaving the cycle at the Arnoldi estimate, maxit) done by device kernels.  A system that converges
+ * inside a cycle leaves through its flag and its kernels return at once; the host reads the flags
+ * between chunks (restart/4 + 1 times per cycle instead of once per step) and skips the remaining
+ * chunks of a cycle in which no system is left.  Results equal the eager form's bit for bit.  The
+ * graphs are captured again after helm_batch_tune; the timing phases do not cover replays.
+ * on == 0 (the default): eager launches, the host checks the estimate after every step; frees the
+ * graphs.  Returns HELM_EINVAL for a NULL batch. */
+int helm_batch_set_graph(helm_batch_t b, int32_t on);
+
 /* Apply M_alpha to every right-hand side of the batch in one set of launches (f[k], u[k] as above,
  * complex128). */
 int sweep_apply_batch(helm_batch_t b, const void* const* f, void* const* u, void* stream);

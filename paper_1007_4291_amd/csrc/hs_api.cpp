@@ -83,6 +83,7 @@ enum Phase { PH_ASSEMBLE = 0, PH_FACTOR, PH_SWEEP_FWD, PH_SWEEP_MID, PH_SWEEP_BW
 struct TimerRec { int phase; int launches; hipEvent_t a, b; };
 struct Timing {
     bool on = false;
+    bool capturing = false;   // launches are being recorded into a graph: no events
     std::vector<TimerRec> recs;
     std::vector<hipEvent_t> pool;
     hipEvent_t get() {
@@ -101,7 +102,7 @@ struct PhaseScope {
     bool live = false;
     PhaseScope(int phase, hipStream_t st, int launches = 1) : s(st) {
         Timing& T = timing();
-        if (!T.on) return;
+        if (!T.on || T.capturing) return;
         rec.phase = phase;
         rec.launches = launches;
         rec.a = T.get();
@@ -170,7 +171,20 @@ struct helm_batch_s {
     bool seg = false;
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // graph form of FGMRES: a restart cycle captured once (on its own stream) as a few graphs that are
+    // replayed, with the convergence bookkeeping on the device: tol / maxit, iterations, final relative
+    // residuals, flags.  gexec: the Arnoldi steps in chunks of kGraphChunk, then the cycle's tail.
+    bool use_graph = false;
+    hipStream_t gstream = nullptr;
+    std::vector<hipGraphExec_t> gexec;
+    DevBuf ctl, it_d, done_d, rr_d;
+    void drop_graph() {
+        for (hipGraphExec_t g : gexec) (void)hipGraphExecDestroy(g);
+        gexec.clear();
+    }
     ~helm_batch_s() {
+        drop_graph();
+        if (gstream) (void)hipStreamDestroy(gstream);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (side) (void)hipStreamDestroy(side);
@@ -282,7 +296,8 @@ extern "C" int helm_matvec(helm_problem_t A, const void* x, int32_t x_prec, void
     if (nrhs == 0) return HELM_OK;
     MvDev mv{x, y, nullptr, nrhs, 0};
     PhaseScope ph(PH_MATVEC, (hipStream_t)stream);
-    launch_matvec(A->pd.as<ProbDev>(), nullptr, mv, nullptr, 1, matvec_blocks(A->n), x_prec, (hipStream_t)stream);
+    launch_matvec(A->pd.as<ProbDev>(), nullptr, mv, nullptr, 1, matvec_blocks(A->n), x_prec, nullptr,
+                  (hipStream_t)stream);
     LAUNCHCHK();
     return HELM_OK;
 }
@@ -624,6 +639,7 @@ extern "C" int sweep_subsolve(sweep_factors_t M, int32_t sub, const void* g, voi
 // workspaces.  Reallocates the workspace only when it has to grow.
 static int build_chain_tables(helm_batch_t b, int ks, int ksm) {
     const int B = b->B, count = b->count;
+    b->drop_graph();   // a captured cycle holds the old tables and schedule
     const int Q = chain_rhs_per_wave(B) / ks, Qm = middle_rhs_per_wave(B) / ksm;
     std::vector<int> order(count);
     for (int p = 0; p < count; ++p) order[p] = p;
@@ -768,12 +784,15 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
     double2* V = b->V.as<double2>();
     char* Z = b->Z.as<char>();
     double2* W = b->W.as<double2>();
+    std::vector<int> sys0(count, 0);
+    for (int p = 1; p < count; ++p) sys0[p] = sys0[p - 1] + b->nrhs[p - 1];
     for (int j = 0; j < kk; ++j)
         for (int p = 0; p < count; ++p) {
             const int64_t blk = (int64_t)b->nrhs[p] * b->N[p];
             ios[(size_t)j * count + p] =
                 IoDev{V + b->voff[p] + j * blk, Z + b->zelem * (b->zoff[p] + j * blk), M[p]->fac.p, M[p]->prop.p};
-            mvz[(size_t)j * count + p] = MvDev{Z + b->zelem * (b->zoff[p] + j * blk), W + b->woff[p], nullptr, b->nrhs[p], 0};
+            mvz[(size_t)j * count + p] = MvDev{Z + b->zelem * (b->zoff[p] + j * blk), W + b->woff[p], nullptr, b->nrhs[p],
+                                                  sys0[p]};
         }
     if ((rc = b->io_sweep.alloc(sizeof(IoDev) * ios.size()))) return rc;
     if ((rc = b->mv_z.alloc(sizeof(MvDev) * mvz.size()))) return rc;
@@ -813,6 +832,10 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
         if ((rc = d->alloc(sizeof(double) * ns))) return rc;
     if ((rc = b->active.alloc(sizeof(int32_t) * ns))) return rc;
     if ((rc = b->cnt.alloc(sizeof(int32_t) * ns))) return rc;
+    if ((rc = b->it_d.alloc(sizeof(int32_t) * ns))) return rc;
+    if ((rc = b->done_d.alloc(sizeof(int32_t) * ns))) return rc;
+    if ((rc = b->rr_d.alloc(sizeof(double) * ns))) return rc;
+    if ((rc = b->ctl.alloc(sizeof(CycleCtl)))) return rc;
     (void)s;
     *out = b.release();
     return HELM_OK;
@@ -924,6 +947,7 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
     hipStream_t s = (hipStream_t)stream;
     const int B = b->B, q = chain_rhs_per_wave(B);
     const int ksm = b->ks_mid;
+    b->drop_graph();
     const int zprec = b->prec == HELM_C128 ? 0 : 1;
     // input: the first Krylov block of every problem, zeroed (timing does not depend on the values)
     for (int p = 0; p < b->count; ++p)
@@ -988,6 +1012,145 @@ extern "C" int sweep_apply_batch(helm_batch_t b, const void* const* f, void* con
     return batch_sweep(b, b->io_apply.as<IoDev>(), 0, nullptr, s);
 }
 
+// r = f - A u into W and beta = ||r|| for every system of the batch (vector tables set per call).
+static int batch_residual(helm_batch_t b, hipStream_t s) {
+    const MvDev none{nullptr, nullptr, nullptr, 0, 0};
+    {
+        PhaseScope ph(PH_MATVEC, s);
+        launch_matvec(b->probs.as<ProbDev>(), b->mv_res.as<MvDev>(), none, b->mv_blk.as<int32_t>(), b->count,
+                      b->mv_blocks, 0, nullptr, s);
+        LAUNCHCHK();
+    }
+    {
+        PhaseScope ph(PH_KRYLOV, s, 2);
+        launch_norms(b->sv.as<SysVec>(), b->tiles.as<int32_t>(), b->nsys, b->ntiles, 0, b->partial.as<double2>(),
+                     b->beta.as<double>(), nullptr, s);
+        LAUNCHCHK();
+    }
+    return HELM_OK;
+}
+
+// Arnoldi step j of the systems flagged in b->active: Z_j = M V_j, W = A Z_j, classical Gram-Schmidt
+// twice against V_0..V_j, Givens update of the Hessenberg column, V_{j+1} = W / ||W||.
+static int batch_arnoldi_step(helm_batch_t b, int j, hipStream_t s) {
+    const int ns = b->nsys, kk = b->restart, nt = b->ntiles, hstride = kk + 1;
+    const SysVec* dsv = b->sv.as<SysVec>();
+    const int32_t* dt = b->tiles.as<int32_t>();
+    const int32_t* act = b->active.as<int32_t>();
+    const MvDev none{nullptr, nullptr, nullptr, 0, 0};
+    const int zprec = b->prec == HELM_C128 ? 0 : 1;
+    int rc = batch_sweep(b, b->io_sweep.as<IoDev>() + (size_t)j * b->count, zprec, act, s);
+    if (rc) return rc;
+    {
+        PhaseScope ph(PH_MATVEC, s);
+        launch_matvec(b->probs.as<ProbDev>(), b->mv_z.as<MvDev>() + (size_t)j * b->count, none, b->mv_blk.as<int32_t>(),
+                      b->count, b->mv_blocks, zprec, act, s);
+        LAUNCHCHK();
+    }
+    PhaseScope phk(PH_KRYLOV, s, 12);
+    double2* Hcol = b->H.as<double2>() + (size_t)j * (kk + 1);   // system stride kk*(kk+1)
+    const int hs_ = kk * (kk + 1);
+    launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, act, s);
+    launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 0, act, s);
+    launch_multiaxpy(dsv, dt, ns, nt, j, Hcol, hs_, act, s);
+    launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, act, s);
+    launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, b->hbuf.as<double2>(), hstride, 0, act, s);
+    launch_multiaxpy(dsv, dt, ns, nt, j, b->hbuf.as<double2>(), hstride, act, s);
+    launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 1, act, s);
+    launch_norms(dsv, dt, ns, nt, 0, b->partial.as<double2>(), b->nrm.as<double>(), act, s);
+    launch_arnoldi_finish(ns, j, kk, b->H.as<double2>(), b->cs.as<double2>(), b->g.as<double2>(), b->nrm.as<double>(),
+                          b->inv.as<double>(), b->est.as<double>(), act, s);
+    launch_scale_to_v(dsv, dt, ns, nt, j + 1, b->inv.as<double>(), act, s);
+    LAUNCHCHK();
+    return HELM_OK;
+}
+
+// x += Z y with y the least-squares solution of the cnt[s] Arnoldi steps of each system.
+static int batch_update(helm_batch_t b, hipStream_t s) {
+    const int zprec = b->prec == HELM_C128 ? 0 : 1;
+    launch_backsolve(b->nsys, b->restart, b->H.as<double2>(), b->g.as<double2>(), b->cnt.as<int32_t>(),
+                     b->y.as<double2>(), s);
+    launch_update_x(b->sv.as<SysVec>(), b->tiles.as<int32_t>(), b->nsys, b->ntiles, b->cnt.as<int32_t>(),
+                    b->y.as<double2>(), b->restart, zprec, s);
+    LAUNCHCHK();
+    return HELM_OK;
+}
+
+// Arnoldi steps per captured graph: after each chunk the host reads the flags once, so a cycle in which
+// every system has converged stops within this many masked steps instead of running to the restart
+// length, at restart / kGraphChunk host round trips per cycle instead of one per step.
+constexpr int kGraphChunk = 4;
+
+// The pieces of the graph form of one restart cycle, for systems flagged active; a system that
+// converges leaves through its flag and its kernels then return at once.  Piece c < chunks: Arnoldi
+// steps [c * kGraphChunk, ...) (the first also starts the cycle); piece `chunks`: the update, the new
+// residual and the flags of the next cycle.  They read only batch-owned device memory, so one capture
+// serves every later call on the batch.
+static int batch_cycle_piece(helm_batch_t b, int piece, hipStream_t s) {
+    const int ns = b->nsys, kk = b->restart;
+    const int chunks = (kk + kGraphChunk - 1) / kGraphChunk;
+    const CycleCtl* ctl = b->ctl.as<CycleCtl>();
+    int rc;
+    if (piece < chunks) {
+        if (piece == 0) {
+            launch_start_cycle(ns, b->beta.as<double>(), b->inv.as<double>(), b->g.as<double2>(), kk + 1, s);
+            launch_scale_to_v(b->sv.as<SysVec>(), b->tiles.as<int32_t>(), ns, b->ntiles, 0, b->inv.as<double>(),
+                              b->active.as<int32_t>(), s);
+            LAUNCHCHK();
+        }
+        for (int j = piece * kGraphChunk; j < std::min(kk, (piece + 1) * kGraphChunk); ++j) {
+            if ((rc = batch_arnoldi_step(b, j, s))) return rc;
+            launch_iter_flags(ns, j, b->est.as<double>(), b->fnorm.as<double>(), ctl, b->it_d.as<int32_t>(),
+                              b->cnt.as<int32_t>(), b->active.as<int32_t>(), s);
+            LAUNCHCHK();
+        }
+        return HELM_OK;
+    }
+    if ((rc = batch_update(b, s))) return rc;
+    if ((rc = batch_residual(b, s))) return rc;
+    launch_cycle_flags(ns, b->beta.as<double>(), b->fnorm.as<double>(), ctl, b->it_d.as<int32_t>(), b->rr_d.as<double>(),
+                       b->done_d.as<int32_t>(), b->active.as<int32_t>(), b->cnt.as<int32_t>(), s);
+    LAUNCHCHK();
+    return HELM_OK;
+}
+
+// Record every piece into a graph on the batch's own stream (a legacy null stream cannot capture)
+// and instantiate it.  No timing events are recorded while capturing.
+static int capture_cycle(helm_batch_t b) {
+    if (!b->gstream) HIPCHK(hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking));
+    const int pieces = (b->restart + kGraphChunk - 1) / kGraphChunk + 1;
+    for (int c = 0; c < pieces; ++c) {
+        HIPCHK(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
+        timing().capturing = true;
+        const int rc = batch_cycle_piece(b, c, b->gstream);
+        timing().capturing = false;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->gstream, &g);
+        if (rc || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            b->drop_graph();
+            return rc ? rc : fail(HELM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        }
+        hipGraphExec_t x = nullptr;
+        const hipError_t ei = hipGraphInstantiateWithFlags(&x, g, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            b->drop_graph();
+            return fail(HELM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        }
+        b->gexec.push_back(x);
+    }
+    return HELM_OK;
+}
+
+extern "C" int helm_batch_set_graph(helm_batch_t b, int32_t on) {
+    if (!b) return fail(HELM_EINVAL, "NULL argument");
+    b->use_graph = on != 0;
+    if (!b->use_graph) b->drop_graph();
+    return HELM_OK;
+}
+
 extern "C" int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* const* u, double tol, int32_t maxit,
                                   int32_t* iters, double* relres, void* stream) {
     if (!b || !f || !u) return fail(HELM_EINVAL, "NULL argument");
@@ -998,9 +1161,9 @@ extern "C" int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* co
     // per-call vector tables
     std::vector<SysVec> sv(ns);
     std::vector<MvDev> mvr(b->count);
-    for (int p = 0; p < b->count; ++p) {
+    for (int p = 0, s0 = 0; p < b->count; s0 += b->nrhs[p], ++p) {
         if (!f[p] || !u[p]) return fail(HELM_EINVAL, "NULL vector for problem %d", p);
-        mvr[p] = MvDev{u[p], b->W.as<double2>() + b->woff[p], f[p], b->nrhs[p], 0};
+        mvr[p] = MvDev{u[p], b->W.as<double2>() + b->woff[p], f[p], b->nrhs[p], s0};
     }
     for (int sidx = 0; sidx < ns; ++sidx) {
         const int p = b->sys_prob[sidx], q = b->sys_rhs[sidx];
@@ -1020,9 +1183,6 @@ extern "C" int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* co
     HIPCHK(hipMemcpy(b->mv_res.p, mvr.data(), sizeof(MvDev) * b->count, hipMemcpyHostToDevice));
     const SysVec* dsv = b->sv.as<SysVec>();
     const int32_t* dt = b->tiles.as<int32_t>();
-    const ProbDev* pd = b->probs.as<ProbDev>();
-    const MvDev none{nullptr, nullptr, nullptr, 0, 0};
-    const int zprec = b->prec == HELM_C128 ? 0 : 1;
 
     std::vector<double> fn(ns), bet(ns), est(ns);
     std::vector<int32_t> it(ns, 0), done(ns, 0), act(ns, 0), cnt(ns, 0);
@@ -1034,82 +1194,88 @@ extern "C" int fgmres_solve_batch(helm_batch_t b, const void* const* f, void* co
     for (int i = 0; i < ns; ++i)
         if (!std::isfinite(fn[i])) return fail(HELM_EINVAL, "right-hand side %d has non-finite values", i);
 
-    const int hstride = kk + 1;
-    while (true) {
-        // r = f - A u (into W), beta = ||r||
-        {
-            PhaseScope ph(PH_MATVEC, s);
-            launch_matvec(pd, b->mv_res.as<MvDev>(), none, b->mv_blk.as<int32_t>(), b->count, b->mv_blocks, 0, s);
-            LAUNCHCHK();
+    int rc;
+    if (b->use_graph) {
+        // Graph form: the host only replays whole cycles and reads the flags between them.
+        const CycleCtl c{tol, maxit, 0};
+        HIPCHK(hipMemcpy(b->ctl.p, &c, sizeof(c), hipMemcpyHostToDevice));
+        launch_zero_i32(b->it_d.as<int32_t>(), ns, s);
+        LAUNCHCHK();
+        if ((rc = batch_residual(b, s))) return rc;
+        launch_cycle_flags(ns, b->beta.as<double>(), b->fnorm.as<double>(), b->ctl.as<CycleCtl>(), b->it_d.as<int32_t>(),
+                           b->rr_d.as<double>(), b->done_d.as<int32_t>(), b->active.as<int32_t>(), b->cnt.as<int32_t>(),
+                           s);
+        LAUNCHCHK();
+        if (b->gexec.empty() && (rc = capture_cycle(b))) return rc;
+        const int chunks = (int)b->gexec.size() - 1;
+        auto any_active = [&]() -> int {
+            if (hipMemcpyAsync(act.data(), b->active.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return -1;
+            for (int i = 0; i < ns; ++i)
+                if (act[i]) return 1;
+            return 0;
+        };
+        while (true) {
+            HIPCHK(hipMemcpyAsync(rr.data(), b->rr_d.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+            const int go = any_active();
+            if (go < 0) return fail(HELM_EHIP, "reading the convergence flags");
+            for (int i = 0; i < ns; ++i)
+                if (!std::isfinite(rr[i])) return fail(HELM_EINVAL, "non-finite residual (system %d)", i);
+            if (!go) break;
+            for (int c = 0; c < chunks; ++c) {
+                HIPCHK(hipGraphLaunch(b->gexec[c], s));
+                if (c + 1 < chunks) {
+                    const int more = any_active();
+                    if (more < 0) return fail(HELM_EHIP, "reading the convergence flags");
+                    if (!more) break;
+                }
+            }
+            HIPCHK(hipGraphLaunch(b->gexec[chunks], s));
         }
-        {
-            PhaseScope ph(PH_KRYLOV, s, 2);
-            launch_norms(dsv, dt, ns, nt, 0, b->partial.as<double2>(), b->beta.as<double>(), nullptr, s);
-            LAUNCHCHK();
-        }
-        HIPCHK(hipMemcpyAsync(bet.data(), b->beta.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(it.data(), b->it_d.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(done.data(), b->done_d.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        int nact = 0;
-        for (int i = 0; i < ns; ++i) {
-            rr[i] = fn[i] > 0.0 ? bet[i] / fn[i] : 0.0;
-            if (!std::isfinite(rr[i])) return fail(HELM_EINVAL, "non-finite residual (system %d)", i);
-            done[i] = (rr[i] <= tol) || fn[i] == 0.0;
-            act[i] = !done[i] && it[i] < maxit;
-            cnt[i] = 0;
-            nact += act[i];
-        }
-        if (nact == 0) break;
-        HIPCHK(hipMemcpyAsync(b->active.p, act.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
-        launch_start_cycle(ns, b->beta.as<double>(), b->inv.as<double>(), b->g.as<double2>(), kk + 1, s);
-        LAUNCHCHK();
-        launch_scale_to_v(dsv, dt, ns, nt, 0, b->inv.as<double>(), b->active.as<int32_t>(), s);
-        LAUNCHCHK();
-        for (int j = 0; j < kk; ++j) {
-            int rc = batch_sweep(b, b->io_sweep.as<IoDev>() + (size_t)j * b->count, zprec, b->active.as<int32_t>(), s);
-            if (rc) return rc;
-            {
-                PhaseScope ph(PH_MATVEC, s);
-                launch_matvec(pd, b->mv_z.as<MvDev>() + (size_t)j * b->count, none, b->mv_blk.as<int32_t>(), b->count,
-                              b->mv_blocks, zprec, s);
-                LAUNCHCHK();
-            }
-            {
-                PhaseScope phk(PH_KRYLOV, s, 12);
-                double2* Hcol = b->H.as<double2>() + (size_t)j * (kk + 1);   // system stride kk*(kk+1)
-                const int hs_ = kk * (kk + 1);
-                // classical Gram-Schmidt, twice
-                launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, b->active.as<int32_t>(), s);
-                launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 0, s);
-                launch_multiaxpy(dsv, dt, ns, nt, j, Hcol, hs_, b->active.as<int32_t>(), s);
-                launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, b->active.as<int32_t>(), s);
-                launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, b->hbuf.as<double2>(), hstride, 0, s);
-                launch_multiaxpy(dsv, dt, ns, nt, j, b->hbuf.as<double2>(), hstride, b->active.as<int32_t>(), s);
-                launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 1, s);
-                launch_norms(dsv, dt, ns, nt, 0, b->partial.as<double2>(), b->nrm.as<double>(), b->active.as<int32_t>(), s);
-                launch_arnoldi_finish(ns, j, kk, b->H.as<double2>(), b->cs.as<double2>(), b->g.as<double2>(),
-                                      b->nrm.as<double>(), b->inv.as<double>(), b->est.as<double>(), b->active.as<int32_t>(), s);
-                launch_scale_to_v(dsv, dt, ns, nt, j + 1, b->inv.as<double>(), b->active.as<int32_t>(), s);
-                LAUNCHCHK();
-            }
-            HIPCHK(hipMemcpyAsync(est.data(), b->est.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+    } else {
+        while (true) {
+            if ((rc = batch_residual(b, s))) return rc;
+            HIPCHK(hipMemcpyAsync(bet.data(), b->beta.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            int still = 0;
+            int nact = 0;
             for (int i = 0; i < ns; ++i) {
-                if (!act[i]) continue;
-                it[i] += 1;
-                cnt[i] = j + 1;
-                const double e = est[i] / fn[i];
-                if (!(e > tol) || it[i] >= maxit) act[i] = 0;   // NaN estimate also ends the cycle
-                still += act[i];
+                rr[i] = fn[i] > 0.0 ? bet[i] / fn[i] : 0.0;
+                if (!std::isfinite(rr[i])) return fail(HELM_EINVAL, "non-finite residual (system %d)", i);
+                done[i] = (rr[i] <= tol) || fn[i] == 0.0;
+                act[i] = !done[i] && it[i] < maxit;
+                cnt[i] = 0;
+                nact += act[i];
             }
-            if (still == 0 || j == kk - 1) break;
+            if (nact == 0) break;
             HIPCHK(hipMemcpyAsync(b->active.p, act.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+            launch_start_cycle(ns, b->beta.as<double>(), b->inv.as<double>(), b->g.as<double2>(), kk + 1, s);
+            LAUNCHCHK();
+            launch_scale_to_v(dsv, dt, ns, nt, 0, b->inv.as<double>(), b->active.as<int32_t>(), s);
+            LAUNCHCHK();
+            for (int j = 0; j < kk; ++j) {
+                if ((rc = batch_arnoldi_step(b, j, s))) return rc;
+                HIPCHK(hipMemcpyAsync(est.data(), b->est.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                int still = 0;
+                for (int i = 0; i < ns; ++i) {
+                    if (!act[i]) continue;
+                    it[i] += 1;
+                    cnt[i] = j + 1;
+                    const double e = est[i] / fn[i];
+                    if (!(e > tol) || it[i] >= maxit) act[i] = 0;   // NaN estimate also ends the cycle
+                    still += act[i];
+                }
+                if (still == 0 || j == kk - 1) break;
+                HIPCHK(hipMemcpyAsync(b->active.p, act.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+            }
+            HIPCHK(hipMemcpyAsync(b->cnt.p, cnt.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+            if ((rc = batch_update(b, s))) return rc;
+            HIPCHK(hipStreamSynchronize(s));
         }
-        HIPCHK(hipMemcpyAsync(b->cnt.p, cnt.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
-        launch_backsolve(ns, kk, b->H.as<double2>(), b->g.as<double2>(), b->cnt.as<int32_t>(), b->y.as<double2>(), s);
-        launch_update_x(dsv, dt, ns, nt, b->cnt.as<int32_t>(), b->y.as<double2>(), kk, zprec, s);
-        LAUNCHCHK();
-        HIPCHK(hipStreamSynchronize(s));
     }
     bool all = true;
     for (int i = 0; i < ns; ++i) {

@@ -99,7 +99,8 @@ constexpr int MV_THREADS = 256;
 
 template <class TX>
 __global__ __launch_bounds__(MV_THREADS) void k_matvec(const ProbDev* __restrict__ probs, const MvDev* __restrict__ io,
-                                                      MvDev io_val, const int32_t* __restrict__ blk_start, int nprob) {
+                                                      MvDev io_val, const int32_t* __restrict__ blk_start, int nprob,
+                                                      const int32_t* __restrict__ active) {
     const int b = blockIdx.x;
     int lo = 0, hi = nprob - 1;                       // last p with blk_start[p] <= b
     while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (blk_start[mid] <= b) lo = mid; else hi = mid - 1; }
@@ -111,6 +112,11 @@ __global__ __launch_bounds__(MV_THREADS) void k_matvec(const ProbDev* __restrict
     const int64_t N = (int64_t)n * n;
     const int64_t t = (int64_t)(b - first) * MV_THREADS + threadIdx.x;
     if (t >= N) return;
+    if (active) {                                     // no right-hand side of this problem left
+        bool any = false;
+        for (int q = 0; q < D.nrhs; ++q) any = any || active[D.sys0 + q] != 0;
+        if (!any) return;
+    }
     const int j = (int)(t / n) + 1, i = (int)(t % n) + 1;
     const double ih2 = P.ih2;
     const double2 is1 = P.is1n[i - 1], is2 = P.is2n[j - 1];
@@ -124,6 +130,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_matvec(const ProbDev* __restrict
     double2* __restrict__ y = (double2*)D.y;
     const double2* __restrict__ f = (const double2*)D.f;
     for (int q = 0; q < D.nrhs; ++q) {
+        if (active && !active[D.sys0 + q]) continue;      // uniform over the block (one problem)
         const TX* xq = x + q * N;
         double2 acc = cmul<double>(dg, ccast<double, decltype(xq->x)>(xq[t]));
         if (i > 1) acc = cfma<double>(axl, ccast<double, decltype(xq->x)>(xq[t - 1]), acc);
@@ -136,11 +143,13 @@ __global__ __launch_bounds__(MV_THREADS) void k_matvec(const ProbDev* __restrict
 }
 
 void launch_matvec(const ProbDev* probs, const MvDev* io, MvDev io_val, const int32_t* blk_start, int nprob,
-                   int total_blocks, int x_prec, hipStream_t s) {
+                   int total_blocks, int x_prec, const int32_t* active, hipStream_t s) {
     if (x_prec == 0)
-        hipLaunchKernelGGL(k_matvec<double2>, dim3(total_blocks), dim3(MV_THREADS), 0, s, probs, io, io_val, blk_start, nprob);
+        hipLaunchKernelGGL(k_matvec<double2>, dim3(total_blocks), dim3(MV_THREADS), 0, s, probs, io, io_val, blk_start, nprob,
+                           active);
     else
-        hipLaunchKernelGGL(k_matvec<float2>, dim3(total_blocks), dim3(MV_THREADS), 0, s, probs, io, io_val, blk_start, nprob);
+        hipLaunchKernelGGL(k_matvec<float2>, dim3(total_blocks), dim3(MV_THREADS), 0, s, probs, io, io_val, blk_start, nprob,
+                           active);
 }
 
 int matvec_blocks(int n) { return (int)(((int64_t)n * n + MV_THREADS - 1) / MV_THREADS); }

@@ -31,16 +31,17 @@ struct MvDev {
     void* y;         // complex128 [nrhs][N]
     const void* f;   // complex128 [nrhs][N] or nullptr
     int32_t nrhs;
-    int32_t pad;
+    int32_t sys0;    // batch system index of right-hand side 0 (for the active mask)
 };
 
 void launch_profiles(const ProfileLayout& L, double2* tab, double h, double omega, double eta_p,
                      double eta_m, double C, hipStream_t s);
 void launch_inv_c2(const double* c, double* ic2, int64_t N, int* bad, hipStream_t s);
 // Batched (io, blk_start device tables over nprob problems) or single problem (io == nullptr,
-// blk_start == nullptr: operands io_val, problem probs[0]).
+// blk_start == nullptr: operands io_val, problem probs[0]).  active: per-system flags indexed by
+// MvDev::sys0 + right-hand side (nullptr: every right-hand side); inactive ones are skipped.
 void launch_matvec(const ProbDev* probs, const MvDev* io, MvDev io_val, const int32_t* blk_start, int nprob,
-                   int total_blocks, int x_prec, hipStream_t s);
+                   int total_blocks, int x_prec, const int32_t* active, hipStream_t s);
 int matvec_blocks(int n);
 
 // a2: factor `nsub` strips of height `bs` (all of one problem). prec 0: complex128 store,
@@ -117,9 +118,9 @@ constexpr int KR_THREADS = 256;
 // partial[t * stride + i] = sum over tile t of conj(V_i) . w   for i = 0..j
 void launch_multidot(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j,
                      double2* partial, int stride, const int32_t* active, hipStream_t s);
-// h[s * hstride + i] (+)= sum of partial over the tiles of system s, i < cnt
+// h[s * hstride + i] (+)= sum of partial over the tiles of system s, i < cnt (active systems only)
 void launch_reduce_partials(const int32_t* tile_start, int nsys, const double2* partial, int stride, int cnt,
-                            double2* h, int hstride, int accumulate, hipStream_t s);
+                            double2* h, int hstride, int accumulate, const int32_t* active, hipStream_t s);
 // w -= sum_{i<=j} h[s][i] V_i
 void launch_multiaxpy(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j,
                       const double2* h, int hstride, const int32_t* active, hipStream_t s);
@@ -142,5 +143,23 @@ void launch_backsolve(int nsys, int k, const double2* H, const double2* g, const
                       hipStream_t s);
 // g[s] = (beta[s], 0, ..., 0), inv[s] = 1/beta[s] (0 if beta == 0)
 void launch_start_cycle(int nsys, const double* beta, double* inv, double2* g, int gstride, hipStream_t s);
+
+// Convergence bookkeeping on the device, for a restart cycle that runs without host round trips
+// (graph replay).  tol and maxit live in device memory so that one captured cycle serves every call.
+struct CycleCtl {
+    double tol;
+    int32_t maxit;
+    int32_t pad_;
+};
+// Start of a cycle: rr[s] = beta[s] / fnorm[s] (0 if fnorm == 0), done[s] = rr <= tol or f == 0,
+// active[s] = !done && it[s] < maxit, cnt[s] = 0.
+void launch_cycle_flags(int nsys, const double* beta, const double* fnorm, const CycleCtl* ctl, const int32_t* it,
+                        double* rr, int32_t* done, int32_t* active, int32_t* cnt, hipStream_t s);
+// After Arnoldi step j, for every active system: it += 1, cnt = j + 1; the system leaves the cycle
+// when est / fnorm <= tol (or is NaN) or it reaches maxit.
+void launch_iter_flags(int nsys, int j, const double* est, const double* fnorm, const CycleCtl* ctl, int32_t* it,
+                       int32_t* cnt, int32_t* active, hipStream_t s);
+// a[0..n) = 0 (a kernel, so that it may sit inside a captured graph)
+void launch_zero_i32(int32_t* a, int n, hipStream_t s);
 
 }  // namespace hs

@@ -68,8 +68,10 @@ __global__ __launch_bounds__(KR_THREADS) void k_multidot(const SysVec* __restric
 
 // h[s * hstride + i] (+)= sum over tiles of system s of partial[t * stride + i]
 __global__ void k_reduce_partials(const int32_t* __restrict__ tile_start, const double2* __restrict__ partial, int stride,
-                                  int cnt, double2* __restrict__ h, int hstride, int accumulate) {
+                                  int cnt, double2* __restrict__ h, int hstride, int accumulate,
+                                  const int32_t* __restrict__ active) {
     const int s = blockIdx.x;
+    if (active && !active[s]) return;
     const int t0 = tile_start[s], t1 = tile_start[s + 1];
     for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
         double2 acc = make_double2(0.0, 0.0);
@@ -245,14 +247,46 @@ __global__ void k_start_g(int nsys, const double* __restrict__ beta, double2* __
     inv[s] = beta[s] > 0.0 ? 1.0 / beta[s] : 0.0;
 }
 
+__global__ void k_cycle_flags(int nsys, const double* __restrict__ beta, const double* __restrict__ fnorm,
+                              const CycleCtl* __restrict__ ctl, const int32_t* __restrict__ it, double* __restrict__ rr,
+                              int32_t* __restrict__ done, int32_t* __restrict__ active, int32_t* __restrict__ cnt) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys) return;
+    const double f = fnorm[s];
+    const double r = f > 0.0 ? beta[s] / f : 0.0;
+    const int d = (r <= ctl->tol) || f == 0.0;
+    rr[s] = r;
+    done[s] = d;
+    active[s] = !d && it[s] < ctl->maxit;
+    cnt[s] = 0;
+}
+
+__global__ void k_iter_flags(int nsys, int j, const double* __restrict__ est, const double* __restrict__ fnorm,
+                             const CycleCtl* __restrict__ ctl, int32_t* __restrict__ it, int32_t* __restrict__ cnt,
+                             int32_t* __restrict__ active) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys || !active[s]) return;
+    const int i = it[s] + 1;
+    it[s] = i;
+    cnt[s] = j + 1;
+    const double e = est[s] / fnorm[s];
+    if (!(e > ctl->tol) || i >= ctl->maxit) active[s] = 0;
+}
+
+__global__ void k_zero_i32(int32_t* __restrict__ a, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
 // ---------------------------------------------------------------------------------------------
 void launch_multidot(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j, double2* partial,
                      int stride, const int32_t* active, hipStream_t s) {
     hipLaunchKernelGGL(k_multidot, dim3(ntiles), dim3(KR_THREADS), 0, s, sv, tile_start, nsys, j, partial, stride, active);
 }
 void launch_reduce_partials(const int32_t* tile_start, int nsys, const double2* partial, int stride, int cnt, double2* h,
-                            int hstride, int accumulate, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nsys), dim3(64), 0, s, tile_start, partial, stride, cnt, h, hstride, accumulate);
+                            int hstride, int accumulate, const int32_t* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nsys), dim3(64), 0, s, tile_start, partial, stride, cnt, h, hstride, accumulate,
+                       active);
 }
 void launch_multiaxpy(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j, const double2* h,
                       int hstride, const int32_t* active, hipStream_t s) {
@@ -284,6 +318,18 @@ void launch_norms(const SysVec* sv, const int32_t* tile_start, int nsys, int nti
 }
 void launch_start_cycle(int nsys, const double* beta, double* inv, double2* g, int gstride, hipStream_t s) {
     hipLaunchKernelGGL(k_start_g, dim3((nsys + 63) / 64), dim3(64), 0, s, nsys, beta, g, gstride, inv);
+}
+void launch_cycle_flags(int nsys, const double* beta, const double* fnorm, const CycleCtl* ctl, const int32_t* it,
+                        double* rr, int32_t* done, int32_t* active, int32_t* cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_cycle_flags, dim3((nsys + 63) / 64), dim3(64), 0, s, nsys, beta, fnorm, ctl, it, rr, done, active,
+                       cnt);
+}
+void launch_iter_flags(int nsys, int j, const double* est, const double* fnorm, const CycleCtl* ctl, int32_t* it,
+                       int32_t* cnt, int32_t* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_iter_flags, dim3((nsys + 63) / 64), dim3(64), 0, s, nsys, j, est, fnorm, ctl, it, cnt, active);
+}
+void launch_zero_i32(int32_t* a, int n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, s, a, n);
 }
 
 }  // namespace hs

@@ -28,7 +28,7 @@ HELM_C64 = 1
 EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_reassemble", "helm_problem_n", "helm_matvec",
            "sweep_factor", "sweep_refactor", "sweep_factor_bytes", "sweep_apply", "sweep_subsolve", "sweep_num_subproblems", "sweep_subproblem_rows",
            "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "sweep_refactor_batch", "helm_batch_tune",
-           "helm_free", "sweep_free",
+           "helm_batch_set_graph", "helm_free", "sweep_free",
            "helm_batch_free", "helm_timing_enable", "helm_timing_read"]
 PHASES = ["assemble", "factor", "sweep_fwd", "sweep_mid", "sweep_bwd", "matvec", "krylov"]
 
@@ -70,6 +70,7 @@ def _load() -> C.CDLL:
         "sweep_refactor_batch": (C.c_int, [vp, vp]),
         "helm_batch_tune": (C.c_int, [vp, C.c_int32, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+        "helm_batch_set_graph": (C.c_int, [vp, C.c_int32]),
         "helm_free": (None, [vp]),
         "sweep_free": (None, [vp]),
         "helm_batch_free": (None, [vp]),
@@ -337,6 +338,10 @@ class Batch:
         rc = _lib.fgmres_solve_batch(self._h, fp, up, tol, maxit, it, rr, C.c_void_p(_stream(stream)))
         _check(rc, allow_notconv=True)
         return SolveResult(u, list(it), list(rr), rc == HELM_OK)
+
+    def use_graph(self, on: bool = True):
+        """Run each FGMRES restart cycle of later solves as one replay of a captured hipGraph (a7)."""
+        _check(_lib.helm_batch_set_graph(self._h, 1 if on else 0))
 
     def tune(self, reps: int = 2, stream=None) -> dict:
         """Pick the fastest sweep schedule for this batch by timing every candidate (a7 autotuner).
