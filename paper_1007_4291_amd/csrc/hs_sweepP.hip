@@ -61,6 +61,17 @@ __device__ __forceinline__ void cfma_rowbcast(float& ax, float& ay, float lx, fl
         : "+v"(ax), "+v"(ay)
         : "v"(lx), "v"(ly), "v"(zx), "v"(zy), "i"(K));
 }
+// The same product starting a sum: acc = l * z_k (no zeroed accumulators to initialise).
+template <int K>
+__device__ __forceinline__ void cmul_rowbcast(float& ax, float& ay, float lx, float ly, float zx, float zy) {
+    asm("s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %4, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%5, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %5, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
+        : "=&v"(ax), "=&v"(ay)
+        : "v"(lx), "v"(ly), "v"(zx), "v"(zy), "i"(K));
+}
 
 }  // namespace
 
@@ -155,7 +166,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     using CF = C2<TF>;
     using SH = SegShape<T, TF, BS>;
     constexpr int RP = SH::RP, Q = SH::Q, NCR = SH::NCR, CB = SH::CB, CSTR = SH::CSTR;
-    static_assert(RP == 16, "segmented chains take strips of at most 16 rows");
+    static_assert(RP == 16 && BS >= 2, "segmented chains take strips of 2 to 16 rows");
     constexpr int PACK = packed_size(BS);
     constexpr int KJ = RP / Q;            // spine: entries of the k-sum per lane
     constexpr int D = 2;                  // column prefetch distance in steps (divides SEG)
@@ -233,7 +244,8 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     for (int k = 0; k < BS; ++k) loff[k] = k >= rr ? packed_index(BS, rr, k) : packed_index(BS, k, rr);
     // Row rr of Lambda^{-1} (staged column) times the row group's vector, whose entry r is this
     // lane's z: in FP32 through row broadcasts, in FP64 through the LDS exchange vector.  Every lane
-    // of the wave takes part (no divergent branch around it).
+    // of the wave takes part (no divergent branch around it).  Only lanes r < BS are read as entries
+    // of the vector, so the z of the padding lanes needs no masking.
     constexpr bool DPP = sizeof(T) == 4;
     auto rowdot = [&](CT z) __attribute__((always_inline)) -> CT {
         if constexpr (DPP) {
@@ -243,10 +255,12 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
 #pragma unroll
             for (int k = 0; k < BS; ++k) lv[k] = ccast<T, TF>(cf[loff[k]]);
             __builtin_amdgcn_sched_barrier(0);
-            float a0x = 0.f, a0y = 0.f, a1x = 0.f, a1y = 0.f;
+            float a0x, a0y, a1x, a1y;
             static_for<BS>([&](auto KC) __attribute__((always_inline)) {
                 constexpr int k = decltype(KC)::value;
-                if constexpr (k & 1) cfma_rowbcast<k>(a1x, a1y, lv[k].x, lv[k].y, z.x, z.y);
+                if constexpr (k == 0) cmul_rowbcast<k>(a0x, a0y, lv[k].x, lv[k].y, z.x, z.y);
+                else if constexpr (k == 1) cmul_rowbcast<k>(a1x, a1y, lv[k].x, lv[k].y, z.x, z.y);
+                else if constexpr (k & 1) cfma_rowbcast<k>(a1x, a1y, lv[k].x, lv[k].y, z.x, z.y);
                 else cfma_rowbcast<k>(a0x, a0y, lv[k].x, lv[k].y, z.x, z.y);
             });
             return mk<T>(a0x + a1x, a0y + a1y);
@@ -270,6 +284,8 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         __amdgpu_buffer_rsrc_t col;
         int tb, cd, row, st;
         uint32_t vb;                 // byte offset of this lane's chunk 0 of column tb
+        int c0;                      // column - 1 of step 0; step j: c0 + cd * j, clamped to [0, n)
+        int ro;                      // (row - 1) * n: the I/O row's element offset
         CT is2;
     };
     auto src_of = [&](int i) __attribute__((always_inline)) -> Src {
@@ -280,6 +296,8 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         s.tb = seg_tbase(s.cd, n, seg);
         s.row = strip_row(ic);
         s.vb = (uint32_t)s.tb * (uint32_t)CB + (uint32_t)(r * 16);
+        s.c0 = s.cd > 0 ? s.tb : n - 1 - s.tb;
+        s.ro = (s.row - 1) * n;
         s.is2 = s.st == 0 ? is2_front : is2_other;
         s.col = buf_rsrc(facbase + sizeof(CF) * ((int64_t)(sub0 + s.st) * n * col_stride<TF>(BS)), (uint32_t)(n * CB));
         return s;
@@ -291,9 +309,21 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         asm volatile("" : "+v"(v));
         return v;
     };
-    auto colof = [&](const Src& s, int t) __attribute__((always_inline)) -> int {
-        const int tc = t < 0 ? 0 : (t >= n ? n - 1 : t);
-        return s.cd > 0 ? tc + 1 : n - tc;
+    // column - 1 of step j, clamped to the strip (steps off the strip read its edge column)
+    auto colm1 = [&](const Src& s, int j) __attribute__((always_inline)) -> int {
+        const int c = late(s.c0) + (s.cd > 0 ? j : -j);
+        return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
+    };
+    // right-hand side (input, complex TI) and output (complex TO) of this lane's system, as buffer
+    // resources: every access is an element offset from a per-strip row offset
+    const __amdgpu_buffer_rsrc_t rin = buf_rsrc(fin, (uint32_t)(N * (int64_t)sizeof(TI)));
+    const __amdgpu_buffer_rsrc_t ryo = buf_rsrc(y, (uint32_t)(N * (int64_t)sizeof(TO)));
+    auto ioload = [&](auto tag, __amdgpu_buffer_rsrc_t rs, int e) __attribute__((always_inline)) -> double2 {
+        using TX = decltype(tag);
+        TX v;
+        buf_ld(v, rs, (uint32_t)e * (uint32_t)sizeof(TX), 0);
+        if constexpr (sizeof(TX) == 16) return v;
+        else return make_double2(v.x, v.y);
     };
 
     // register ring: the column chunks, one input value and one workspace value per step
@@ -321,7 +351,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         uint32_t d[sizeof(CF) / 4];
 #pragma unroll
         for (int i = 0; i < (int)(sizeof(CF) / 4); ++i)
-            d[i] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[DW + i], 0x150 + LN, 0xF, 0xF, false);
+            d[i] = (uint32_t)__builtin_amdgcn_mov_dpp((int)v[DW + i], 0x150 + LN, 0xF, 0xF, false);
         CF out;
         if constexpr (sizeof(CF) == 8) out = make_float2(__uint_as_float(d[0]), __uint_as_float(d[1]));
         else out = make_double2(__hiloint2double((int)d[1], (int)d[0]), __hiloint2double((int)d[3], (int)d[2]));
@@ -335,13 +365,11 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const uint32_t vo = late(s.vb) + (uint32_t)j * (uint32_t)CB;
 #pragma unroll
         for (int c = 0; c < NCR; ++c) rk[u][c] = buf_ld16(s.col, vo + (uint32_t)(c * RP * 16), 0);
-        const int t = late(s.tb) + j;
-        const int col = colof(s, t);
         if constexpr (PK == 1) {
-            if (MODE == MODE_FWD) ra[u] = ld2(fin + (int64_t)(s.row - 1) * n + col - 1);
-            else if (first) ra[u] = ld2(y + (int64_t)(cmid - 1) * n + col - 1);
+            if (MODE == MODE_FWD) ra[u] = ioload(TI{}, rin, s.ro + colm1(s, j));
+            else if (first) ra[u] = ioload(TO{}, ryo, (cmid - 1) * n + colm1(s, j));
         } else if constexpr (PK == 7) {
-            if (MODE == MODE_BWD) ra[u] = ld2(y + (int64_t)(s.row - 1) * n + col - 1);
+            if (MODE == MODE_BWD) ra[u] = ioload(TO{}, ryo, s.ro + colm1(s, j));
         }
         // B1 takes the last D forward products from registers (their loads would precede the stores)
         if constexpr (PK == 3 || PK == 7) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
@@ -360,10 +388,12 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
 
     // one forward step: F1 (PK 1) builds g_t from the input and the previous layer row and stores it,
     // F3 (PK 3) loads it back and stores w_t
-    auto fstep = [&](auto PKC, int j, auto UC, const Src& s, bool first, bool full) __attribute__((always_inline)) {
+    // (full: the strip's rows are all outputs (front strip); wout: this lane's row is an output)
+    auto fstep = [&](auto PKC, int j, auto UC, const Src& s, bool first, bool full, bool wout)
+                     __attribute__((always_inline)) {
         constexpr int PK = decltype(PKC)::value, u = decltype(UC)::value;
         const int t = late(s.tb) + j;
-        const bool valid = segok && t >= 0 && t < n;
+        const bool valid = segok && (uint32_t)t < (uint32_t)n;
         stage(u);
         wave_sync();
         // cross-lane reads first, with every lane active (a DPP source lane outside the exec mask
@@ -372,20 +402,20 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         CT g;
         if constexpr (PK == 1) {
             const CT sL = ringscalar(std::integral_constant<int, MODE == MODE_FWD ? XCOL_APREV : XCOL_ANEXT>{}, u);
-            const int col = colof(s, t);
+            const int c = colm1(s, j);
             if (MODE == MODE_FWD) {
                 CT gv = ccast<T, double>(ra[u]);
-                if (!full) gv = csub<T>(gv, cmul<T>(sL, ylr[col - 1]));
-                g = (full ? rok : slot) ? gv : mk<T>(0, 0);
+                if (!full) gv = csub<T>(gv, cmul<T>(sL, ylr[c]));
+                g = wout ? gv : mk<T>(0, 0);
             } else {
-                const CT yp = first ? ccast<T, double>(ra[u]) : ylr[col - 1];
+                const CT yp = first ? ccast<T, double>(ra[u]) : ylr[c];
                 g = slot ? cmul<T>(sL, yp) : mk<T>(0, 0);
             }
             buf_st(g, wrs, late(wlane), (uint32_t)j * wstep);
         } else {
             g = rg[u];
         }
-        const CT w = rowdot(csel<T>(rok, cadd<T>(g, carry), mk<T>(0, 0)));
+        const CT w = rowdot(cadd<T>(g, carry));
         const CT ne = cscale<T>(cmul<T>(sE, s.is2), (T)-1);
         if constexpr (PK == 3) {
             buf_st(w, wrs, late(wlane), (uint32_t)j * wstep);
@@ -395,14 +425,14 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         wave_sync();
     };
     // one backward step: B1 (PK 5) from a zero value above, B3 (PK 7) writes the strip's outputs
-    auto bstep = [&](auto PKC, int j, auto UC, const Src& s, bool full) __attribute__((always_inline)) {
+    auto bstep = [&](auto PKC, int j, auto UC, const Src& s, bool wout) __attribute__((always_inline)) {
         constexpr int PK = decltype(PKC)::value, u = decltype(UC)::value;
         const int t = late(s.tb) + j;
-        const bool valid = segok && t >= 0 && t < n;
+        const bool valid = segok && (uint32_t)t < (uint32_t)n;
         stage(u);
         wave_sync();
         const CT sE = ringscalar(std::integral_constant<int, XCOL_E>{}, u);
-        const CT v = rowdot(csel<T>(rok, cmul<T>(s.is2, xb), mk<T>(0, 0)));
+        const CT v = rowdot(cmul<T>(s.is2, xb));
         CT wj = rg[u];
         if constexpr (PK == 5) {
             if (j >= SEG - D) wj = wl[D - 1 - u];   // j - (SEG - D) == D - 1 - u
@@ -410,10 +440,10 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const CT xn = cfms<T>(sE, v, wj);
         xb = csel<T>(valid, xn, xb);
         if constexpr (PK == 7) {
-            const int col = colof(s, t);
+            const int c = colm1(s, j);
             const CT yval = MODE == MODE_BWD ? csub<T>(ccast<T, double>(ra[u]), xb) : xb;
-            if (valid && (full ? rok : slot)) gst(y + (int64_t)(s.row - 1) * n + col - 1, cvt_out<TO, T>(yval));
-            if (valid && slot) ylr[col - 1] = yval;
+            if (valid && wout) buf_st(cvt_out<TO, T>(yval), ryo, (uint32_t)(s.ro + c) * (uint32_t)sizeof(TO), 0);
+            if (valid && slot) ylr[c] = yval;
         }
         wave_sync();
     };
@@ -427,11 +457,12 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
                        __attribute__((always_inline)) {
         constexpr int NPK = decltype(NPKC)::value;
         const bool full = s.st == 0;
+        const bool wout = full ? rok : slot;
         for (int gi = 0; gi < NG; ++gi) {
             static_for<D>([&](auto UC) __attribute__((always_inline)) {
                 constexpr int u = decltype(UC)::value;
                 const int j = gi * D + u;
-                fstep(PKC, j, UC, s, first, full);
+                fstep(PKC, j, UC, s, first, full, wout);
                 hook(j);
                 if (gi + 1 < NG) issue(PKC, j + D, UC, s, first);
                 else issue(NPKC, (NPK == 5 || NPK == 7) ? SEG - 1 - u : u, UC, ns, nfirst);
@@ -441,13 +472,13 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     auto phase_b = [&](auto PKC, const Src& s, auto NPKC, const Src& ns, bool nfirst, auto&& hook)
                        __attribute__((always_inline)) {
         constexpr int NPK = decltype(NPKC)::value;
-        const bool full = s.st == 0;
+        const bool wout = s.st == 0 ? rok : slot;
         for (int gi = 0; gi < NG; ++gi) {
             static_for<D>([&](auto UC) __attribute__((always_inline)) {
                 constexpr int u = decltype(UC)::value;
                 const int k = gi * D + u;                  // position in the phase
                 const int j = SEG - 1 - k;
-                bstep(PKC, j, UC, s, full);
+                bstep(PKC, j, UC, s, wout);
                 hook(k);
                 if (gi + 1 < NG) issue(PKC, j - D, UC, s, false);
                 else issue(NPKC, (NPK == 5 || NPK == 7) ? SEG - 1 - u : u, UC, ns, nfirst);
