@@ -66,6 +66,8 @@ def test_null_handles_rejected(hs):
     assert L.fgmres_solve(None, None, None, None, 1, 20, 1e-6, 10, None, None, None) == hs.HELM_EINVAL
     assert L.helm_batch_create(None, None, None, 0, 20, None, None) == hs.HELM_EINVAL
     assert L.fgmres_solve_batch(None, None, None, 1e-6, 10, None, None, None) == hs.HELM_EINVAL
+    assert L.helm_batch_set_graph(None, 1) == hs.HELM_EINVAL
+    assert L.helm_batch_tune(None, 1, None, None, None, None, None) == hs.HELM_EINVAL
     assert L.helm_problem_n(None) == -1
     assert L.sweep_factor_bytes(None) == 0
     assert L.sweep_num_subproblems(None) == -1

@@ -57,8 +57,10 @@ def _same(res, ref):
         assert bool((u == r).all())
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_graph_solve_equals_eager(hs, torch, prec):
+@pytest.mark.parametrize("prec,seg", [(0, "1"), (1, "1"), (1, "0")])
+def test_graph_solve_equals_eager(hs, torch, monkeypatch, prec, seg):
+    # seg "0": the plain chain kernels (k-split schedule) inside the captured cycle
+    monkeypatch.setenv("HELM_SWEEP_SEG", seg)
     b, fs, _keep = _batch(hs, torch, prec)
     ref = b.solve(fs, tol=1e-8)
     assert ref.converged
@@ -66,7 +68,7 @@ def test_graph_solve_equals_eager(hs, torch, prec):
     _log("eager iters", ref.iters)
     b.use_graph(True)
     for rep in range(3):
-        _log("graph solve", prec, rep)
+        _log("graph solve", prec, seg, rep)
         res = b.solve(fs, [torch.zeros_like(f) for f in fs], tol=1e-8)   # fresh output buffers
         _same(res, ref)
         b.apply(fs)                                   # eager work on the batch between the calls
