@@ -33,36 +33,69 @@ __device__ __forceinline__ double2 block_sum(double2 v, double2* red) {
 
 constexpr int PER_THREAD = KR_TILE / KR_THREADS;
 
+// Basis vectors per pass of the dot and update kernels: their loads are issued together (the last
+// group re-reads V_j for the missing ones, from cache, and does not use them).
+constexpr int KR_GROUP = 4;
+
 // partial[t * stride + i] = sum_tile conj(V_i) w, i = 0..j
 __global__ __launch_bounds__(KR_THREADS) void k_multidot(const SysVec* __restrict__ sv, const int32_t* __restrict__ tile_start,
                                                          int nsys, int j, double2* __restrict__ partial, int stride,
                                                          const int32_t* __restrict__ active) {
-    __shared__ double2 red[KR_THREADS / 64];
+    __shared__ double2 red[KR_GROUP][KR_THREADS / 64];
     const int b = blockIdx.x;
     const int s = tile_system(tile_start, nsys, b);
     if (active && !active[s]) return;
     const SysVec V = sv[s];
     const int64_t base = (int64_t)(b - tile_start[s]) * KR_TILE;
     double2 wv[PER_THREAD];
+    int64_t ix[PER_THREAD];
+    bool ok[PER_THREAD];
 #pragma unroll
     for (int e = 0; e < PER_THREAD; ++e) {
         const int64_t idx = base + e * KR_THREADS + threadIdx.x;
-        wv[e] = idx < V.len ? V.w[idx] : make_double2(0.0, 0.0);
+        ok[e] = idx < V.len;
+        ix[e] = ok[e] ? idx : V.len - 1;
+        wv[e] = ok[e] ? gld(gptr(V.w) + idx) : make_double2(0.0, 0.0);
     }
-    for (int i = 0; i <= j; ++i) {
-        const double2* vi = V.v + (int64_t)i * V.vstride;
-        double2 acc = make_double2(0.0, 0.0);
+    for (int i0 = 0; i0 <= j; i0 += KR_GROUP) {
+        double2 a[KR_GROUP][PER_THREAD];
 #pragma unroll
-        for (int e = 0; e < PER_THREAD; ++e) {
-            const int64_t idx = base + e * KR_THREADS + threadIdx.x;
-            if (idx < V.len) {
-                const double2 a = vi[idx];
-                acc.x = fma(a.x, wv[e].x, fma(a.y, wv[e].y, acc.x));
-                acc.y = fma(a.x, wv[e].y, fma(-a.y, wv[e].x, acc.y));
+        for (int g = 0; g < KR_GROUP; ++g) {
+            const HS_GLOBAL double2* vi = gptr(V.v) + (int64_t)min(i0 + g, j) * V.vstride;
+#pragma unroll
+            for (int e = 0; e < PER_THREAD; ++e) a[g][e] = gld(vi + ix[e]);
+        }
+        double2 acc[KR_GROUP];
+#pragma unroll
+        for (int g = 0; g < KR_GROUP; ++g) {
+            acc[g] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int e = 0; e < PER_THREAD; ++e) {
+                if (ok[e]) {
+                    acc[g].x = fma(a[g][e].x, wv[e].x, fma(a[g][e].y, wv[e].y, acc[g].x));
+                    acc[g].y = fma(a[g][e].x, wv[e].y, fma(-a[g][e].y, wv[e].x, acc[g].y));
+                }
+            }
+            // wave sums, as in block_sum
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                acc[g].x += __shfl_xor(acc[g].x, off);
+                acc[g].y += __shfl_xor(acc[g].y, off);
             }
         }
-        const double2 tot = block_sum(acc, red);
-        if (threadIdx.x == 0) partial[(int64_t)b * stride + i] = tot;
+        const int w = threadIdx.x >> 6;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int g = 0; g < KR_GROUP; ++g) red[g][w] = acc[g];
+        }
+        __syncthreads();
+        if (threadIdx.x < KR_GROUP && i0 + (int)threadIdx.x <= j) {
+            const int g = threadIdx.x;
+            double2 t = red[g][0];
+            for (int k = 1; k < KR_THREADS / 64; ++k) t = cadd<double>(t, red[g][k]);
+            partial[(int64_t)b * stride + i0 + g] = t;
+        }
     }
 }
 
@@ -81,7 +114,7 @@ __global__ void k_reduce_partials(const int32_t* __restrict__ tile_start, const 
     }
 }
 
-// w -= sum_{i<=j} h_i V_i
+// w -= sum_{i<=j} h_i V_i, subtracted in increasing i for every element
 __global__ __launch_bounds__(KR_THREADS) void k_multiaxpy(const SysVec* __restrict__ sv, const int32_t* __restrict__ tile_start,
                                                           int nsys, int j, const double2* __restrict__ h, int hstride,
                                                           const int32_t* __restrict__ active) {
@@ -91,14 +124,35 @@ __global__ __launch_bounds__(KR_THREADS) void k_multiaxpy(const SysVec* __restri
     const SysVec V = sv[s];
     const double2* hs_ = h + (int64_t)s * hstride;
     const int64_t base = (int64_t)(b - tile_start[s]) * KR_TILE;
+    double2 acc[PER_THREAD];
+    int64_t ix[PER_THREAD];
+    bool ok[PER_THREAD];
 #pragma unroll
     for (int e = 0; e < PER_THREAD; ++e) {
         const int64_t idx = base + e * KR_THREADS + threadIdx.x;
-        if (idx >= V.len) continue;
-        double2 acc = V.w[idx];
-        for (int i = 0; i <= j; ++i) acc = cfms<double>(hs_[i], V.v[(int64_t)i * V.vstride + idx], acc);
-        V.w[idx] = acc;
+        ok[e] = idx < V.len;
+        ix[e] = ok[e] ? idx : V.len - 1;
+        acc[e] = gld(gptr(V.w) + ix[e]);
     }
+    for (int i0 = 0; i0 <= j; i0 += KR_GROUP) {
+        double2 a[KR_GROUP][PER_THREAD];
+#pragma unroll
+        for (int g = 0; g < KR_GROUP; ++g) {
+            const HS_GLOBAL double2* vi = gptr(V.v) + (int64_t)min(i0 + g, j) * V.vstride;
+#pragma unroll
+            for (int e = 0; e < PER_THREAD; ++e) a[g][e] = gld(vi + ix[e]);
+        }
+#pragma unroll
+        for (int g = 0; g < KR_GROUP; ++g) {
+            if (i0 + g > j) break;
+            const double2 hg = hs_[i0 + g];
+#pragma unroll
+            for (int e = 0; e < PER_THREAD; ++e) acc[e] = cfms<double>(hg, a[g][e], acc[e]);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < PER_THREAD; ++e)
+        if (ok[e]) gst(gptr(V.w) + ix[e], acc[e]);
 }
 
 // V_dst = w * scale[s]
