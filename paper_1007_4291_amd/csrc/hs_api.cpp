@@ -1047,13 +1047,18 @@ static int batch_arnoldi_step(helm_batch_t b, int j, hipStream_t s) {
                       b->count, b->mv_blocks, zprec, act, s);
         LAUNCHCHK();
     }
-    PhaseScope phk(PH_KRYLOV, s, 12);
+    PhaseScope phk(PH_KRYLOV, s, j + 1 <= KR_FUSE ? 10 : 11);
     double2* Hcol = b->H.as<double2>() + (size_t)j * (kk + 1);   // system stride kk*(kk+1)
     const int hs_ = kk * (kk + 1);
     launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, act, s);
     launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 0, act, s);
-    launch_multiaxpy(dsv, dt, ns, nt, j, Hcol, hs_, act, s);
-    launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, act, s);
+    if (j + 1 <= KR_FUSE) {
+        // first update and second dot products in one pass over V (same values as the two kernels)
+        launch_multiaxpy_dot(dsv, dt, ns, nt, j, Hcol, hs_, b->partial.as<double2>(), hstride, act, s);
+    } else {
+        launch_multiaxpy(dsv, dt, ns, nt, j, Hcol, hs_, act, s);
+        launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, act, s);
+    }
     launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, b->hbuf.as<double2>(), hstride, 0, act, s);
     launch_multiaxpy(dsv, dt, ns, nt, j, b->hbuf.as<double2>(), hstride, act, s);
     launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 1, act, s);

@@ -124,6 +124,12 @@ void launch_reduce_partials(const int32_t* tile_start, int nsys, const double2* 
 // w -= sum_{i<=j} h[s][i] V_i
 void launch_multiaxpy(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j,
                       const double2* h, int hstride, const int32_t* active, hipStream_t s);
+// Basis vectors the fused update + dot kernel keeps in registers per element (j + 1 <= KR_FUSE).
+constexpr int KR_FUSE = 24;
+// k_multiaxpy with h, then the dot products of the updated w with V_0..V_j into partial (as
+// launch_multidot), in one pass over V; j + 1 <= KR_FUSE.
+void launch_multiaxpy_dot(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j, const double2* h,
+                          int hstride, double2* partial, int stride, const int32_t* active, hipStream_t s);
 // V_dst = w * scale[s]
 void launch_scale_to_v(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int dst,
                        const double* scale, const int32_t* active, hipStream_t s);

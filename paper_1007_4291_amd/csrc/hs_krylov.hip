@@ -155,6 +155,77 @@ __global__ __launch_bounds__(KR_THREADS) void k_multiaxpy(const SysVec* __restri
         if (ok[e]) gst(gptr(V.w) + ix[e], acc[e]);
 }
 
+// The first update of a Gram-Schmidt pair fused with the second pass's dot products, for up to
+// KR_FUSE basis vectors: per element, the basis values stay in registers between the update
+// w -= sum_{i<=j} h_i V_i (subtracted in increasing i, as k_multiaxpy) and the products
+// partial[t * stride + i] = sum_tile conj(V_i) w (summed over the elements in order and reduced by
+// the same tree as k_multidot), so the pass reads V once instead of twice and gives the same values.
+__global__ __launch_bounds__(KR_THREADS) void k_multiaxpy_dot(const SysVec* __restrict__ sv,
+                                                              const int32_t* __restrict__ tile_start, int nsys, int j,
+                                                              const double2* __restrict__ h, int hstride,
+                                                              double2* __restrict__ partial, int stride,
+                                                              const int32_t* __restrict__ active) {
+    __shared__ double2 red[KR_GROUP][KR_THREADS / 64];
+    const int b = blockIdx.x;
+    const int s = tile_system(tile_start, nsys, b);
+    if (active && !active[s]) return;
+    const SysVec V = sv[s];
+    const double2* hs_ = h + (int64_t)s * hstride;
+    const int64_t base = (int64_t)(b - tile_start[s]) * KR_TILE;
+    double2 d[KR_FUSE];
+#pragma unroll
+    for (int i = 0; i < KR_FUSE; ++i) d[i] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int e = 0; e < PER_THREAD; ++e) {
+        const int64_t idx = base + e * KR_THREADS + threadIdx.x;
+        const bool ok = idx < V.len;
+        const int64_t ix = ok ? idx : V.len - 1;
+        double2 v[KR_FUSE];
+#pragma unroll
+        for (int i = 0; i < KR_FUSE; ++i)
+            if (i <= j) v[i] = gld(gptr(V.v) + (int64_t)i * V.vstride + ix);
+        double2 w = gld(gptr(V.w) + ix);
+#pragma unroll
+        for (int i = 0; i < KR_FUSE; ++i)
+            if (i <= j) w = cfms<double>(hs_[i], v[i], w);
+        if (ok) {
+            gst(gptr(V.w) + ix, w);
+#pragma unroll
+            for (int i = 0; i < KR_FUSE; ++i) {
+                if (i <= j) {
+                    d[i].x = fma(v[i].x, w.x, fma(v[i].y, w.y, d[i].x));
+                    d[i].y = fma(v[i].x, w.y, fma(-v[i].y, w.x, d[i].y));
+                }
+            }
+        }
+    }
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i0 = 0; i0 < KR_FUSE; i0 += KR_GROUP) {
+        if (i0 > j) break;
+#pragma unroll
+        for (int g = 0; g < KR_GROUP; ++g) {
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                d[i0 + g].x += __shfl_xor(d[i0 + g].x, off);
+                d[i0 + g].y += __shfl_xor(d[i0 + g].y, off);
+            }
+        }
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int g = 0; g < KR_GROUP; ++g) red[g][wv] = d[i0 + g];
+        }
+        __syncthreads();
+        if (threadIdx.x < KR_GROUP && i0 + (int)threadIdx.x <= j) {
+            const int g = threadIdx.x;
+            double2 t = red[g][0];
+            for (int k = 1; k < KR_THREADS / 64; ++k) t = cadd<double>(t, red[g][k]);
+            partial[(int64_t)b * stride + i0 + g] = t;
+        }
+    }
+}
+
 // V_dst = w * scale[s]
 __global__ __launch_bounds__(KR_THREADS) void k_scale_to_v(const SysVec* __restrict__ sv, const int32_t* __restrict__ tile_start,
                                                            int nsys, int dst, const double* __restrict__ scale,
@@ -345,6 +416,11 @@ void launch_reduce_partials(const int32_t* tile_start, int nsys, const double2* 
 void launch_multiaxpy(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j, const double2* h,
                       int hstride, const int32_t* active, hipStream_t s) {
     hipLaunchKernelGGL(k_multiaxpy, dim3(ntiles), dim3(KR_THREADS), 0, s, sv, tile_start, nsys, j, h, hstride, active);
+}
+void launch_multiaxpy_dot(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j, const double2* h,
+                          int hstride, double2* partial, int stride, const int32_t* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_multiaxpy_dot, dim3(ntiles), dim3(KR_THREADS), 0, s, sv, tile_start, nsys, j, h, hstride, partial,
+                       stride, active);
 }
 void launch_scale_to_v(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int dst, const double* scale,
                        const int32_t* active, hipStream_t s) {
