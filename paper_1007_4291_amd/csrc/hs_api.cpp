@@ -1047,7 +1047,7 @@ static int batch_arnoldi_step(helm_batch_t b, int j, hipStream_t s) {
                       b->count, b->mv_blocks, zprec, act, s);
         LAUNCHCHK();
     }
-    PhaseScope phk(PH_KRYLOV, s, j + 1 <= KR_FUSE ? 10 : 11);
+    PhaseScope phk(PH_KRYLOV, s, j + 1 <= KR_FUSE ? 9 : 10);
     double2* Hcol = b->H.as<double2>() + (size_t)j * (kk + 1);   // system stride kk*(kk+1)
     const int hs_ = kk * (kk + 1);
     launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, act, s);
@@ -1060,9 +1060,10 @@ static int batch_arnoldi_step(helm_batch_t b, int j, hipStream_t s) {
         launch_multidot(dsv, dt, ns, nt, j, b->partial.as<double2>(), hstride, act, s);
     }
     launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, b->hbuf.as<double2>(), hstride, 0, act, s);
-    launch_multiaxpy(dsv, dt, ns, nt, j, b->hbuf.as<double2>(), hstride, act, s);
     launch_reduce_partials(dt, ns, b->partial.as<double2>(), hstride, j + 1, Hcol, hs_, 1, act, s);
-    launch_norms(dsv, dt, ns, nt, 0, b->partial.as<double2>(), b->nrm.as<double>(), act, s);
+    // second update, with the norm partials of the result (the dot partials are consumed above)
+    launch_multiaxpy(dsv, dt, ns, nt, j, b->hbuf.as<double2>(), hstride, act, s, b->partial.as<double2>());
+    launch_norm_finish(dt, ns, b->partial.as<double2>(), b->nrm.as<double>(), act, s);
     launch_arnoldi_finish(ns, j, kk, b->H.as<double2>(), b->cs.as<double2>(), b->g.as<double2>(), b->nrm.as<double>(),
                           b->inv.as<double>(), b->est.as<double>(), act, s);
     launch_scale_to_v(dsv, dt, ns, nt, j + 1, b->inv.as<double>(), act, s);

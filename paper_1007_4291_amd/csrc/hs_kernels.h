@@ -121,9 +121,10 @@ void launch_multidot(const SysVec* sv, const int32_t* tile_start, int nsys, int 
 // h[s * hstride + i] (+)= sum of partial over the tiles of system s, i < cnt (active systems only)
 void launch_reduce_partials(const int32_t* tile_start, int nsys, const double2* partial, int stride, int cnt,
                             double2* h, int hstride, int accumulate, const int32_t* active, hipStream_t s);
-// w -= sum_{i<=j} h[s][i] V_i
+// w -= sum_{i<=j} h[s][i] V_i; npart (optional, ntiles entries): per-tile |w|^2 partial sums of the
+// result, for launch_norm_finish
 void launch_multiaxpy(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j,
-                      const double2* h, int hstride, const int32_t* active, hipStream_t s);
+                      const double2* h, int hstride, const int32_t* active, hipStream_t s, double2* npart = nullptr);
 // Basis vectors the fused update + dot kernel keeps in registers per element (j + 1 <= KR_FUSE).
 constexpr int KR_FUSE = 24;
 // k_multiaxpy with h, then the dot products of the updated w with V_0..V_j into partial (as
@@ -139,6 +140,9 @@ void launch_update_x(const SysVec* sv, const int32_t* tile_start, int nsys, int 
 // ||vec|| per system, vec = w (which 0) or f (which 1); partial needs ntiles entries
 void launch_norms(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int which,
                   double2* partial, double* out, const int32_t* active, hipStream_t s);
+// out[s] = sqrt(sum of partial[t].x over the tiles of system s) (the second half of launch_norms)
+void launch_norm_finish(const int32_t* tile_start, int nsys, const double2* partial, double* out, const int32_t* active,
+                        hipStream_t s);
 // Column j of the Hessenberg matrix H[s][j][0..k] of every active system: set H[j+1][j] = nrm[s],
 // apply the previous Givens rotations, form the new one, rotate g; est[s] = |g[j+1]|,
 // inv_norm[s] = 1/nrm[s] (0 if nrm == 0).

@@ -114,10 +114,12 @@ __global__ void k_reduce_partials(const int32_t* __restrict__ tile_start, const 
     }
 }
 
-// w -= sum_{i<=j} h_i V_i, subtracted in increasing i for every element
+// w -= sum_{i<=j} h_i V_i, subtracted in increasing i for every element; with npart, also the tile's
+// partial sum of |w|^2 of the result into npart[tile] (as k_norm_partials: same elements, order, tree)
 __global__ __launch_bounds__(KR_THREADS) void k_multiaxpy(const SysVec* __restrict__ sv, const int32_t* __restrict__ tile_start,
                                                           int nsys, int j, const double2* __restrict__ h, int hstride,
-                                                          const int32_t* __restrict__ active) {
+                                                          const int32_t* __restrict__ active, double2* __restrict__ npart) {
+    __shared__ double2 red[KR_THREADS / 64];
     const int b = blockIdx.x;
     const int s = tile_system(tile_start, nsys, b);
     if (active && !active[s]) return;
@@ -153,6 +155,14 @@ __global__ __launch_bounds__(KR_THREADS) void k_multiaxpy(const SysVec* __restri
 #pragma unroll
     for (int e = 0; e < PER_THREAD; ++e)
         if (ok[e]) gst(gptr(V.w) + ix[e], acc[e]);
+    if (npart) {
+        double nacc = 0.0;
+#pragma unroll
+        for (int e = 0; e < PER_THREAD; ++e)
+            if (ok[e]) nacc = fma(acc[e].x, acc[e].x, fma(acc[e].y, acc[e].y, nacc));
+        const double2 tot = block_sum(make_double2(nacc, 0.0), red);
+        if (threadIdx.x == 0) npart[b] = tot;
+    }
 }
 
 // The first update of a Gram-Schmidt pair fused with the second pass's dot products, for up to
@@ -414,8 +424,9 @@ void launch_reduce_partials(const int32_t* tile_start, int nsys, const double2* 
                        active);
 }
 void launch_multiaxpy(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j, const double2* h,
-                      int hstride, const int32_t* active, hipStream_t s) {
-    hipLaunchKernelGGL(k_multiaxpy, dim3(ntiles), dim3(KR_THREADS), 0, s, sv, tile_start, nsys, j, h, hstride, active);
+                      int hstride, const int32_t* active, hipStream_t s, double2* npart) {
+    hipLaunchKernelGGL(k_multiaxpy, dim3(ntiles), dim3(KR_THREADS), 0, s, sv, tile_start, nsys, j, h, hstride, active,
+                       npart);
 }
 void launch_multiaxpy_dot(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int j, const double2* h,
                           int hstride, double2* partial, int stride, const int32_t* active, hipStream_t s) {
@@ -444,6 +455,10 @@ void launch_backsolve(int nsys, int k, const double2* H, const double2* g, const
 void launch_norms(const SysVec* sv, const int32_t* tile_start, int nsys, int ntiles, int which, double2* partial,
                   double* out, const int32_t* active, hipStream_t s) {
     hipLaunchKernelGGL(k_norm_partials, dim3(ntiles), dim3(KR_THREADS), 0, s, sv, tile_start, nsys, which, partial, active);
+    hipLaunchKernelGGL(k_norm_finish, dim3((nsys + 63) / 64), dim3(64), 0, s, tile_start, nsys, partial, out, active);
+}
+void launch_norm_finish(const int32_t* tile_start, int nsys, const double2* partial, double* out, const int32_t* active,
+                        hipStream_t s) {
     hipLaunchKernelGGL(k_norm_finish, dim3((nsys + 63) / 64), dim3(64), 0, s, tile_start, nsys, partial, out, active);
 }
 void launch_start_cycle(int nsys, const double* beta, double* inv, double2* g, int gstride, hipStream_t s) {
