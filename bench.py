@@ -11,6 +11,7 @@ Metric: preconditioned solves/sec, reported as RHS*N unknowns/s (right-hand side
 per problem, per second), FP32-factor batched form vs the plain FP64 form on the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|lens255|grf1023|const63]
+                       [--prec c64|c128] [--fp64-steps K64] [--graph-steps KG] [--no-cpu-baseline]
 """
 from __future__ import annotations
 

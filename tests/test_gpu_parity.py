@@ -201,6 +201,30 @@ def test_fgmres_cfg1_parity(hs, torch, prec):
         assert err <= 1e-4
 
 
+def test_fgmres_long_restart_parity(hs, torch):
+    """FGMRES(30) on a case the oracle solves in 32 iterations: Arnoldi steps j >= 24 use the
+    separate update and dot kernels, earlier ones the fused kernel; FP64 factors, against the
+    oracle's FGMRES with the same restart and tolerance."""
+    n, om = 47, 2 * math.pi * 10
+    op = OH.Params(n=n, omega=om, pml_w=6, mpml_w=3)
+    c = workloads.velocity_layered(n, seed=3)
+    f = workloads.random_rhs(n, 1, seed=4)
+    A = _gpu_problem(hs, torch, op, c)
+    F = hs.Factors(A, hs.HELM_C128)
+    res = hs.fgmres(A, F, torch.as_tensor(f, device="cuda"), restart=30, tol=1e-11)
+    Ao = OH.assemble(op, c)
+    Mo = OS.factor(op, c)
+    ro = OK.fgmres(lambda v: Ao @ v, lambda v: OS.apply_sweep(Mo, v), f[0], 30, 1e-11)
+    u = res.u.cpu().numpy()[0]
+    true_rel = np.linalg.norm(f[0] - Ao @ u) / np.linalg.norm(f[0])
+    err = _rel(u, ro.x)
+    _log(f"  iters gpu {res.iters} oracle {ro.iters}; true relres {true_rel:.2e}; err vs oracle {err:.2e}")
+    assert ro.iters > 25
+    assert res.converged and true_rel <= 1e-11
+    assert abs(res.iters[0] - ro.iters) <= 1
+    assert err <= 1e-8
+
+
 def test_fgmres_cfg2_fp64_parity(hs, torch):
     """Config 2 (n = 255, lens, Gaussian source, widths 12) in FP64 against the oracle."""
     pr = workloads.cfg2()
