@@ -77,20 +77,25 @@ class Runner:
         self.batch = hs.Batch(self.A, self.M, [p.nrhs for p in probs], restart=restart)
         self.tol = probs[0].tol
         self.last = None
+        self.split = []          # (setup s, solve s) of every step: assemble + factor, then FGMRES
 
     def step(self):
+        t0 = time.perf_counter()
         for A, c in zip(self.A, self.c):
             A.reassemble(c)
-        self.batch.refactor()
+        self.batch.refactor()           # synchronises
+        t1 = time.perf_counter()
         for u in self.u:
             u.zero_()
-        self.last = self.batch.solve(self.f, self.u, tol=self.tol, maxit=400)
+        self.last = self.batch.solve(self.f, self.u, tol=self.tol, maxit=400)   # synchronises
+        self.split.append((t1 - t0, time.perf_counter() - t1))
         return self.last
 
 
 def timed(runner, torch, steps, warmup):
     for _ in range(warmup):
         runner.step()
+    runner.split.clear()
     runner.hs.timing_read(reset=True)
     runner.hs.timing_enable(True)
     torch.cuda.synchronize()
@@ -104,6 +109,24 @@ def timed(runner, torch, steps, warmup):
     runner.hs.timing_enable(False)
     phases = runner.hs.timing_read(reset=True)
     return (t1 - t0) / steps, phases
+
+
+def copy_bandwidth(torch, gib=2):
+    """Measured HBM bandwidth of a plain device copy (read + write bytes / time, best of 5), GB/s."""
+    a = torch.ones(gib * 2**27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    best = 1e30
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    nbytes = 2 * a.numel() * 8
+    del a, b
+    torch.cuda.empty_cache()
+    return nbytes / best / 1e9
 
 
 def sweep_bytes_flops(probs, B, fac_bytes, vin, vout):
@@ -209,6 +232,8 @@ def main():
     print(f"[bench] schedule {schedule}", file=sys.stderr, flush=True)
     t_step, ph = timed(run, torch, a.steps, a.warmup)
     res = run.last
+    setup_s = sorted(x[0] for x in run.split)
+    solve_s = sorted(x[1] for x in run.split)
     print(f"[bench] {a.prec}: {t_step * 1e3:.1f} ms/step, iters {min(res.iters)}-{max(res.iters)}",
           file=sys.stderr, flush=True)
     value = tot_unknowns / t_step
@@ -231,6 +256,10 @@ def main():
             "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
             "launches": n_f + n_b, "algorithmic_bytes_per_launch": int(bytes_per_launch),
             "tflops": round(fl / (avg_ms * 1e-3) / 1e12, 4)}
+    roof["frac_fp32_vector"] = round(roof["tflops"] / 157.3, 5)      # of the 157.3 TFLOP/s FP32 vector peak
+    hbm_meas = copy_bandwidth(torch)
+    roof["measured_copy_gbs"] = round(hbm_meas, 1)
+    roof["frac_of_measured_copy"] = round(achieved / hbm_meas, 5)
 
     out = {"metric": "preconditioned solves/sec (RHS*N unknowns/s) at 1e-6 residual; FP32-batched vs FP64",
            "value": value, "unit": "RHS*N unknowns/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -240,6 +269,8 @@ def main():
                       "restart": probs[0].restart, "tol": probs[0].tol,
                       "factor_prec": a.prec, "krylov_prec": "f64"},
            "solves_per_s": nsys / t_step,
+           "t_solve_ms_median": round(solve_s[len(solve_s) // 2] * 1e3, 2),
+           "t_setup_ms_median": round(setup_s[len(setup_s) // 2] * 1e3, 2),
            "iters": {"min": min(res.iters), "max": max(res.iters), "mean": float(np.mean(res.iters))},
            "max_true_relres": max(res.relres),
            "phase_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in ph.items()},
