@@ -247,9 +247,9 @@ def main():
     avg_ms = (ms_f + ms_b) / max(1, n_f + n_b)
     bytes_per_launch = (b0 + b1) / 2
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    kind = "segmented" if schedule.get("segmented") else "plain"
+    kind = f"segmented-{schedule.get('waves')}w" if schedule.get("segmented") else "plain"
     traffic = measured_traffic(a.workload, a.prec, kind)
-    kname = ("k_sweepP (segmented chains)" if kind == "segmented"
+    kname = (f"k_sweepP (segmented chains, {schedule.get('waves')}-wave workgroups)" if schedule.get("segmented")
              else f"k_sweep{'2' if schedule.get('waves') == 2 else ''} (chains)") + " forward/backward launches"
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": int(traffic) if traffic else None,

@@ -176,13 +176,16 @@ int sweep_apply_batch(helm_batch_t b, const void* const* f, void* const* u, void
  * batch's own first Krylov block, zeroed) for every candidate schedule and keeps the fastest for all
  * later solves and applications of the batch.  Candidates: the segmented chains (every strip solve
  * split into 16-column segments joined by a short sequential pass over segment propagators; strip
- * heights <= 13 and n <= 1024, or 512 for complex128 factors), and the plain chains with two waves
+ * heights <= 13 and n <= 1024, or 512 for complex128 factors) in workgroups of the fewest waves that
+ * hold one right-hand side of the largest problem and of 2x and 4x as many where they fit the LDS
+ * (several right-hand sides of a problem per workgroup), and the plain chains with two waves
  * per chain (backward and forward pass of a strip pair on separate waves, heights <= 17) or one,
  * each with the number of row groups every right-hand side's block products are split over (1, 2,
  * 4, ... dividing the row groups of a wave).  Each is run `reps` times after one warm-up.  Results
  * are unchanged up to rounding order.
- *   ksplit, waves, segmented: host (may be NULL): the chosen plain-chain split and waves per chain,
- *                             and 1 if the segmented chains won (then ksplit / waves are unused)
+ *   ksplit, waves, segmented: host (may be NULL): 1 in segmented if the segmented chains won, then
+ *                             waves = their workgroup's waves and ksplit = 0; else the plain
+ *                             chains' split and waves per chain
  *   ms: host (may be NULL): its time per application, milliseconds
  * Overwrites the batch's Krylov work space; synchronises `stream`. */
 int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32_t* ksplit, int32_t* waves,

@@ -167,7 +167,7 @@ struct helm_batch_s {
     int nfsubs = 0, nmsubs = 0;
     // segmented sweep: propagator work of all problems, chain table, workgroup waves; kind 1 selects it
     DevBuf propw, segch, segws;
-    int npropw = 0, nsegch = 0, seg_wg = 0, kind = 0;
+    int npropw = 0, nsegch = 0, seg_wg = 0, seg_maxn = 0, kind = 0;
     bool seg = false;
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -316,6 +316,16 @@ static int seg_env() {
     const char* e = std::getenv("HELM_SWEEP_SEG");
     return e ? std::atoi(e) : -1;
 }
+// Waves per segmented workgroup to aim for (HELM_SEG_WG; 0: the fewest that hold one right-hand side
+// of the largest problem), halved until the workgroup fits the LDS.
+static int seg_wg_target(int prec, int B, const std::vector<int>& n) {
+    const char* e = std::getenv("HELM_SEG_WG");
+    int t = e ? std::atoi(e) : 0;
+    int wmin = 1, maxn = 1;
+    for (int v : n) { wmin = std::max(wmin, (seg_count(v) + 3) / 4); maxn = std::max(maxn, v); }
+    while (t > wmin && !seg_fits(prec, B, t, maxn)) t /= 2;
+    return t > wmin ? t : 0;
+}
 
 // Run the a2 kernels for every strip of M's problem and check the pivots.
 static int factor_into(sweep_factors_t M, hipStream_t s) {
@@ -401,7 +411,7 @@ extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_
     if ((rc = M->status.alloc(sizeof(int)))) return rc;
     HIPCHK(hipMemcpy(M->subs.p, S.data(), sizeof(SubDev) * S.size(), hipMemcpyHostToDevice));
     // segmented sweep: propagators of every segment of every front strip (not the middle)
-    M->seg = seg_supported(B) && seg_waves_rhs(n) <= seg_max_waves(prec == HELM_C128 ? 0 : 1, B);
+    M->seg = seg_fits(prec == HELM_C128 ? 0 : 1, B, seg_waves_rhs(n), n);
     if (M->seg) {
         const int Sg = seg_count(n);
         const int64_t per_strip = seg_strip_elems(n, B);
@@ -482,10 +492,11 @@ static void rhs_grouping(int B, int max_nrhs, int* Q, int* ks, int* Qm, int* ksm
 // go, largest first, to the XCD with the least work so far; shorter XCD queues are padded with
 // entries of no right-hand side (nq = 0), which return at once.  HELM_SEG_XCD=0 keeps the plain order.
 constexpr int kXcds = 8;
-static std::vector<ChainDev> seg_table(const std::vector<int>& n, const std::vector<int>& nrhs, int* wg) {
+static std::vector<ChainDev> seg_table(const std::vector<int>& n, const std::vector<int>& nrhs, int target, int* wg) {
     const int count = (int)n.size();
     int w = 1;
     for (int p = 0; p < count; ++p) w = std::max(w, seg_waves_rhs(n[p]));
+    w = std::max(w, target);
     std::vector<int> order(count), base(count + 1, 0);
     for (int p = 0; p < count; ++p) { order[p] = p; base[p + 1] = base[p] + nrhs[p]; }
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n[a] > n[c]; });
@@ -554,7 +565,8 @@ static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
     M->nmids = (int)md.size();
     M->kind = 0;
     if (M->seg) {
-        const std::vector<ChainDev> sc = seg_table({n}, {nrhs}, &M->seg_wg);
+        const std::vector<ChainDev> sc = seg_table({n}, {nrhs}, seg_wg_target(M->prec == HELM_C128 ? 0 : 1, B, {n}),
+                                                   &M->seg_wg);
         if ((rc = M->segch.alloc(sizeof(ChainDev) * sc.size()))) return rc;
         HIPCHK(hipMemcpy(M->segch.p, sc.data(), sizeof(ChainDev) * sc.size(), hipMemcpyHostToDevice));
         M->nsegch = (int)sc.size();
@@ -582,7 +594,7 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
         PhaseScope ph(PH_SWEEP_FWD, s);
         const bool ok = M->kind == 1
                             ? launch_chains_seg(B, M->prec, vec_prec, vec_prec, 0, pd, M->segch.as<ChainDev>(), M->nsegch,
-                                                nullptr, io, M->seg_wg, nullptr, M->segws.p, s)
+                                                nullptr, io, M->seg_wg, M->A->n, nullptr, M->segws.p, s)
                             : run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd,
                                          M->chains.as<ChainDev>(), M->nchains, nullptr, io, M->spill.p, nullptr, s);
         if (!ok) return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
@@ -598,7 +610,7 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
         PhaseScope ph(PH_SWEEP_BWD, s);
         if (M->kind == 1)
             launch_chains_seg(B, M->prec, vec_prec, vec_prec, 1, pd, M->segch.as<ChainDev>(), M->nsegch, nullptr, io,
-                              M->seg_wg, nullptr, M->segws.p, s);
+                              M->seg_wg, M->A->n, nullptr, M->segws.p, s);
         else
             run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
                        nullptr, io, M->spill.p, nullptr, s);
@@ -634,6 +646,29 @@ extern "C" int sweep_subsolve(sweep_factors_t M, int32_t sub, const void* g, voi
 // ------------------------------------------------------------------------------------------------
 // a6 / a7: batched FGMRES
 // ------------------------------------------------------------------------------------------------
+// Segmented chain table of a batch for a workgroup-size target (0: the fewest waves that hold one
+// right-hand side of its largest problem), and its workspace (reallocated only to grow).  Clears
+// b->seg when the workgroup does not fit.
+static int build_seg_table(helm_batch_t b, int target) {
+    b->drop_graph();   // a captured cycle holds the old table
+    std::vector<int> nv(b->count);
+    for (int p = 0; p < b->count; ++p) nv[p] = b->A[p]->n;
+    int wg = 0;
+    const std::vector<ChainDev> sc = seg_table(nv, b->nrhs, target, &wg);
+    if (!seg_fits(b->prec == HELM_C128 ? 0 : 1, b->B, wg, b->seg_maxn)) {
+        b->seg = false;
+        return HELM_OK;
+    }
+    int rc;
+    if ((rc = b->segch.alloc(sizeof(ChainDev) * sc.size()))) return rc;
+    HIPCHK(hipMemcpy(b->segch.p, sc.data(), sizeof(ChainDev) * sc.size(), hipMemcpyHostToDevice));
+    b->nsegch = (int)sc.size();
+    b->seg_wg = wg;
+    const size_t wsb = compute_elem(b->prec) * (size_t)seg_ws_elems(b->nsegch, wg);
+    if (b->segws.bytes < wsb && (rc = b->segws.alloc(wsb))) return rc;
+    return HELM_OK;
+}
+
 // Chain and middle tables of a batch for a given k-split (right-hand sides per wave = row groups per
 // wave / k-split): problem-fronts in decreasing n, right-hand-side groups of each, and their
 // workspaces.  Reallocates the workspace only when it has to grow.
@@ -759,13 +794,9 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
     if (b->seg) {
         std::vector<int> nv(count);
         for (int p = 0; p < count; ++p) nv[p] = A[p]->n;
-        const std::vector<ChainDev> sc = seg_table(nv, b->nrhs, &b->seg_wg);
-        if (b->seg_wg > seg_max_waves(b->prec == HELM_C128 ? 0 : 1, B)) b->seg = false;
+        b->seg_maxn = *std::max_element(nv.begin(), nv.end());
+        if ((rc = build_seg_table(b.get(), seg_wg_target(b->prec == HELM_C128 ? 0 : 1, B, nv)))) return rc;
         if (b->seg) {
-            if ((rc = b->segch.alloc(sizeof(ChainDev) * sc.size()))) return rc;
-            HIPCHK(hipMemcpy(b->segch.p, sc.data(), sizeof(ChainDev) * sc.size(), hipMemcpyHostToDevice));
-            b->nsegch = (int)sc.size();
-            if ((rc = b->segws.alloc(compute_elem(b->prec) * (size_t)seg_ws_elems(b->nsegch, b->seg_wg)))) return rc;
             std::vector<PropDev> pw;
             for (int p = 0; p < count; ++p) {
                 std::vector<PropDev> one(M[p]->npropw);
@@ -915,7 +946,7 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int3
         PhaseScope ph(PH_SWEEP_FWD, s);
         const bool ok = b->kind == 1
                             ? launch_chains_seg(b->B, b->prec, 0, out_prec, 0, pd, b->segch.as<ChainDev>(), b->nsegch, io,
-                                                none, b->seg_wg, active, b->segws.p, s)
+                                                none, b->seg_wg, b->seg_maxn, active, b->segws.p, s)
                             : run_chains(b->waves, b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd,
                                          b->chains.as<ChainDev>(), b->nchains, io, none, b->spill.p, active, s);
         if (!ok) return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
@@ -931,7 +962,7 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int3
         PhaseScope ph(PH_SWEEP_BWD, s);
         if (b->kind == 1)
             launch_chains_seg(b->B, b->prec, 0, out_prec, 1, pd, b->segch.as<ChainDev>(), b->nsegch, io, none, b->seg_wg,
-                              active, b->segws.p, s);
+                              b->seg_maxn, active, b->segws.p, s);
         else
             run_chains(b->waves, b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io,
                        none, b->spill.p, active, s);
@@ -955,7 +986,7 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    int best_ks = b->ks_chain, best_w = b->waves, best_kind = b->kind, rc = HELM_OK;
+    int best_ks = b->ks_chain, best_w = b->waves, best_kind = b->kind, best_segt = 0, rc = HELM_OK;
     double best = 1e300;
     auto time_one = [&](double* per) -> int {
         const IoDev* io = b->io_sweep.as<IoDev>();
@@ -972,9 +1003,19 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
         return HELM_OK;
     };
     if (b->seg) {
+        // segmented chains with workgroups of the fewest waves that hold one right-hand side of the
+        // largest problem, and of 2x and 4x as many (several right-hand sides per workgroup) where they fit
+        const int prec01 = b->prec == HELM_C128 ? 0 : 1;
+        int wmin = 1;
+        for (int p = 0; p < b->count; ++p) wmin = std::max(wmin, seg_waves_rhs(b->A[p]->n));
         b->kind = 1;
-        double per = 0;
-        if ((rc = time_one(&per)) == HELM_OK && per < best) { best = per; best_kind = 1; }
+        for (int t : {0, 2 * wmin, 4 * wmin}) {
+            if (t && !seg_fits(prec01, B, t, b->seg_maxn)) continue;
+            if ((rc = build_seg_table(b, t))) break;
+            double per = 0;
+            if ((rc = time_one(&per))) break;
+            if (per < best) { best = per; best_kind = 1; best_segt = t; }
+        }
     }
     b->kind = 0;
     for (int w = (B <= 17 ? 2 : 1); w >= 1 && rc == HELM_OK; --w)
@@ -990,10 +1031,11 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     if ((rc = build_chain_tables(b, best_ks, ksm))) return rc;
+    if (b->seg && (rc = build_seg_table(b, best_kind == 1 ? best_segt : 0))) return rc;
     b->waves = best_w;
     b->kind = best_kind;
     if (ksplit) *ksplit = best_kind == 1 ? 0 : best_ks;
-    if (waves) *waves = best_kind == 1 ? 0 : best_w;
+    if (waves) *waves = best_kind == 1 ? b->seg_wg : best_w;
     if (segmented) *segmented = best_kind;
     if (ms) *ms = best;
     return HELM_OK;

@@ -71,15 +71,17 @@ bool launch_chains2(int B, int prec, int in_prec, int out_prec, int phase, int k
 // Segmented chains (strip solves partitioned into SEG-column segments): one workgroup of `waves`
 // waves per chain; ChainDev::wrhs = waves per right-hand side (ceil(segments / 4)), nq right-hand
 // sides per workgroup.  io[p].prop must hold the problem's propagators (launch_prop).  Returns false
-// for strip heights without an instance or a workgroup beyond the LDS.
+// for strip heights without an instance or a workgroup beyond the LDS.  max_n: the largest n of
+// the problems in the table (sizes the shared propagator area).
 // ws: workspace of seg_ws_elems(nchains, waves) complex elements of the compute precision.
 bool launch_chains_seg(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
-                       const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves,
+                       const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves, int max_n,
                        const int32_t* active, void* ws, hipStream_t s);
 int64_t seg_ws_elems(int nchains, int waves);
 bool seg_supported(int B);
-// Largest workgroup (in waves) of the segmented chains that fits the LDS.
-int seg_max_waves(int prec, int B);
+// LDS of a segmented workgroup of `waves` waves for problems up to max_n, and whether it fits.
+size_t seg_lds_bytes(int prec, int B, int waves, int max_n);
+bool seg_fits(int prec, int B, int waves, int max_n);
 // Segment propagators of front strips, one wave per work item (Q segments of one strip).
 bool launch_prop(int B, int prec, const ProbDev* probs, const PropDev* work, int nwork, hipStream_t s);
 bool launch_middle(int B, int prec, int in_prec, int out_prec, int ksplit, const ProbDev* probs,

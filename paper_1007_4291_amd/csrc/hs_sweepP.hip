@@ -145,13 +145,13 @@ template <class T, class TF, int BS> struct SegShape {
     static constexpr int CSTR = NCR * RP + 2;
     // exchange vectors: LDS only in FP64 (FP32 takes the vector through row broadcasts)
     static constexpr int XZ = sizeof(T) == 8 ? 64 : 0;
-    // the strip's segment propagators: LDS only in FP32, up to 4 segments per wave
-    static constexpr int PHL = sizeof(T) == 4 ? Q * BS * BS : 0;
     // LDS bytes per wave: staged columns, exchange vectors, 2 spine vectors per segment slot, layer
-    // rows, propagators.  (Each spine vector holds the per-segment contributions q / p and the values
-    // entering the segments c / x in turn: their lifetimes are separated by barriers.)
-    static constexpr int LDS_WAVE = Q * CSTR * 16 + XZ * (int)sizeof(C2<T>) + 2 * Q * RP * (int)sizeof(C2<T>) +
-                                    64 * (int)sizeof(C2<T>) + PHL * (int)sizeof(C2<TF>);
+    // rows.  (Each spine vector holds the per-segment contributions q / p and the values entering the
+    // segments c / x in turn: their lifetimes are separated by barriers.)  After the waves' areas, in
+    // FP32 only, the strip's segment propagators, shared by every right-hand side of the workgroup
+    // (seg_lds_bytes).
+    static constexpr int LDS_FIXED = Q * CSTR * 16 + XZ * (int)sizeof(C2<T>) + 2 * Q * RP * (int)sizeof(C2<T>) +
+                                     64 * (int)sizeof(C2<T>);
 };
 
 // Workgroups of up to 16 waves in FP32 (128 registers per lane) and 8 in FP64.
@@ -183,6 +183,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     CT* const xv = cv;
     CT* const ylay = cv + nw * Q * RP;                           // [nw*64]: layer rows by column
     CF* const phl = (CF*)(ylay + nw * 64);                       // [segments][BS*BS] (FP32 only)
+    static_assert(SH::LDS_FIXED % 16 == 0, "the propagator area must stay 16-byte aligned");
 
     const ChainDev ch = chains[blockIdx.x];
     if (ch.nq == 0) return;                                      // padding entry of the table
@@ -626,24 +627,32 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
 // ---------------------------------------------------------------------------------------------
 bool seg_supported(int B) { return B == 4 || B == 5 || B == 7 || B == 9 || B == 13; }
 
-template <class T, class TF> static int seg_waves_typed(int B) {
-    int per = 0;
+template <class T, class TF> static size_t seg_lds_typed(int B, int waves, int max_n) {
+    int fixed = 0;
     switch (B) {
-        case 4: per = SegShape<T, TF, 4>::LDS_WAVE; break;
-        case 5: per = SegShape<T, TF, 5>::LDS_WAVE; break;
-        case 7: per = SegShape<T, TF, 7>::LDS_WAVE; break;
-        case 9: per = SegShape<T, TF, 9>::LDS_WAVE; break;
-        case 13: per = SegShape<T, TF, 13>::LDS_WAVE; break;
+        case 4: fixed = SegShape<T, TF, 4>::LDS_FIXED; break;
+        case 5: fixed = SegShape<T, TF, 5>::LDS_FIXED; break;
+        case 7: fixed = SegShape<T, TF, 7>::LDS_FIXED; break;
+        case 9: fixed = SegShape<T, TF, 9>::LDS_FIXED; break;
+        case 13: fixed = SegShape<T, TF, 13>::LDS_FIXED; break;
         default: return 0;
     }
-    return std::min(SegWaves<T>::MAX, (160 * 1024) / per);
+    const int64_t segs = (max_n + SEG - 1) / SEG;
+    const int64_t props = sizeof(T) == 4 ? ((segs * B * B + 1) & ~(int64_t)1) * (int64_t)sizeof(C2<TF>) : 0;
+    return (size_t)fixed * waves + (size_t)props;
 }
-int seg_max_waves(int prec, int B) { return prec == 0 ? seg_waves_typed<double, double>(B) : seg_waves_typed<float, float>(B); }
+size_t seg_lds_bytes(int prec, int B, int waves, int max_n) {
+    return prec == 0 ? seg_lds_typed<double, double>(B, waves, max_n) : seg_lds_typed<float, float>(B, waves, max_n);
+}
+bool seg_fits(int prec, int B, int waves, int max_n) {
+    const int maxw = prec == 0 ? SegWaves<double>::MAX : SegWaves<float>::MAX;
+    const size_t lds = seg_lds_bytes(prec, B, waves, max_n);
+    return seg_supported(B) && waves >= 1 && waves <= maxw && lds > 0 && lds <= 160 * 1024;
+}
 
 template <class T, class TF, class TI, class TO, int BV, int MODE>
 static bool segp_launch(const ProbDev* probs, const ChainDev* chains, int nb, const IoDev* io, IoDev iov, int waves,
-                        const int32_t* act, void* ws, hipStream_t s) {
-    const size_t lds = (size_t)SegShape<T, TF, BV>::LDS_WAVE * waves;
+                        const int32_t* act, void* ws, size_t lds, hipStream_t s) {
     if (lds > 160 * 1024) return false;
     hipLaunchKernelGGL((k_sweepP<T, TF, TI, TO, BV, MODE>), dim3(nb), dim3(64 * waves), lds, s, probs, chains, io, iov, act,
                        (C2<T>*)ws);
@@ -652,10 +661,10 @@ static bool segp_launch(const ProbDev* probs, const ChainDev* chains, int nb, co
 
 template <class T, class TF, class TI, class TO, int MODE>
 static bool segp_typed(int bs, const ProbDev* probs, const ChainDev* chains, int nb, const IoDev* io, IoDev iov,
-                       int waves, const int32_t* act, void* ws, hipStream_t s) {
+                       int waves, const int32_t* act, void* ws, size_t lds, hipStream_t s) {
     switch (bs) {
 #define HS_CASE(BV) \
-    case BV: return segp_launch<T, TF, TI, TO, BV, MODE>(probs, chains, nb, io, iov, waves, act, ws, s);
+    case BV: return segp_launch<T, TF, TI, TO, BV, MODE>(probs, chains, nb, io, iov, waves, act, ws, lds, s);
         HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13)
 #undef HS_CASE
         default: return false;
@@ -664,30 +673,32 @@ static bool segp_typed(int bs, const ProbDev* probs, const ChainDev* chains, int
 
 template <int MODE>
 static bool segp_prec(int bs, int prec, int in_prec, int out_prec, const ProbDev* probs, const ChainDev* chains, int nb,
-                      const IoDev* io, IoDev iov, int waves, const int32_t* act, void* ws, hipStream_t s) {
+                      const IoDev* io, IoDev iov, int waves, const int32_t* act, void* ws, size_t lds, hipStream_t s) {
     if (prec == 0) {
         if (in_prec == 0 && out_prec == 0)
-            return segp_typed<double, double, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, s);
+            return segp_typed<double, double, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds,
+                                                                      s);
         return false;
     }
     if (in_prec == 0 && out_prec == 0)
-        return segp_typed<float, float, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, s);
+        return segp_typed<float, float, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds, s);
     if (in_prec == 0 && out_prec == 1)
-        return segp_typed<float, float, double2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, s);
+        return segp_typed<float, float, double2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds, s);
     if (in_prec == 1 && out_prec == 1)
-        return segp_typed<float, float, float2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, s);
+        return segp_typed<float, float, float2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds, s);
     return false;
 }
 
 bool launch_chains_seg(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
-                       const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves,
+                       const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves, int max_n,
                        const int32_t* active, void* ws, hipStream_t s) {
     if (nchains <= 0) return true;
-    if (waves < 1 || waves > seg_max_waves(prec, B)) return false;
+    if (!seg_fits(prec, B, waves, max_n)) return false;
+    const size_t lds = seg_lds_bytes(prec, B, waves, max_n);
     return phase == 0 ? segp_prec<MODE_FWD>(B, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, waves, active,
-                                            ws, s)
+                                            ws, lds, s)
                       : segp_prec<MODE_BWD>(B, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, waves, active,
-                                            ws, s);
+                                            ws, lds, s);
 }
 
 int64_t seg_ws_elems(int nchains, int waves) { return (int64_t)nchains * SEG * 64 * waves; }

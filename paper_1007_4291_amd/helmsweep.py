@@ -346,8 +346,9 @@ class Batch:
     def tune(self, reps: int = 2, stream=None) -> dict:
         """Pick the fastest sweep schedule for this batch by timing every candidate (a7 autotuner).
 
-        Overwrites the batch's Krylov work space.  Returns {"segmented", "ksplit", "waves", "ms_per_apply"}
-        (ksplit / waves describe the plain chains and are 0 when the segmented chains won)."""
+        Overwrites the batch's Krylov work space.  Returns {"segmented", "ksplit", "waves", "ms_per_apply"}:
+        for the segmented chains waves is their workgroup size and ksplit 0; for the plain chains the
+        split and the waves per chain."""
         ks, wv, sg, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
         _check(_lib.helm_batch_tune(self._h, int(reps), C.c_void_p(_stream(stream)), C.byref(ks), C.byref(wv),
                                     C.byref(sg), C.byref(ms)))

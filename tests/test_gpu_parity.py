@@ -434,6 +434,39 @@ def test_sweep_segmented_parity(hs, torch, monkeypatch, n, w, prec):
     assert e1 <= btol and e2 <= btol
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sweep_segmented_workgroup_sizes(hs, torch, monkeypatch, prec):
+    """Segmented workgroups that hold several right-hand sides of a problem (the autotuner's larger
+    workgroup candidates, forced through HELM_SEG_WG; complex128 halves a target beyond its 8-wave
+    limit) give, bit for bit, the default grouping's M f, which matches the oracle."""
+    monkeypatch.setenv("HELM_SWEEP_SEG", "1")
+    specs = [(129, 8, 5), (64, 8, 3)]      # strip height 9: 9 and 4 segments, 3 and 1 waves per RHS
+    probs, facs, fs, fo, mos = [], [], [], [], []
+    for n, w, R in specs:
+        op = OH.Params(n=n, omega=2 * math.pi * n / 8, alpha=2.0, pml_w=w, mpml_w=w)
+        c = workloads.velocity_layered(n, seed=n + 29)
+        A = _gpu_problem(hs, torch, op, c)
+        probs.append(A)
+        facs.append(hs.Factors(A, prec))
+        f = workloads.random_rhs(n, R, seed=n + 31)
+        fo.append(f)
+        fs.append(torch.as_tensor(f, device="cuda"))
+        mos.append(OS.factor(op, c))
+    outs = {}
+    for tgt in ("0", "6", "12"):
+        monkeypatch.setenv("HELM_SEG_WG", tgt)
+        _log("segmented workgroup target", tgt, "prec", prec)
+        b = hs.Batch(probs, facs, [R for _, _, R in specs], restart=4)
+        outs[tgt] = [u.cpu().numpy() for u in b.apply(fs)]
+        del b
+    for tgt in ("6", "12"):
+        for a, r in zip(outs[tgt], outs["0"]):
+            assert np.array_equal(a, r)
+    tol = 1e-10 if prec == 0 else 1e-4
+    for u, f, Mo in zip(outs["0"], fo, mos):
+        assert _rel(u, OS.apply_sweep(Mo, f)) <= tol
+
+
 def test_sweep_segmented_equals_chains(hs, torch, monkeypatch):
     """On the bench's strip height and a ragged n, a batched FGMRES solve (which freezes converged
     systems) takes the same iterations with the segmented and the plain chains, to the same answer."""
