@@ -331,9 +331,10 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     chunk16 rk[D][NCR];
     double2 ra[D];
     CT rg[D];
-    // Workspace: the right-hand side g_t of each step (F1 -> F3), then the forward product w_t
-    // (F3 -> B1, B3), laid out [workgroup][step][thread] so that every access is one coalesced
-    // 8- or 16-byte word per lane; the register file cannot hold 16 steps of it besides the rest.
+    // Workspace: the forward product w_t of each step (F3 -> B1, B3), laid out
+    // [workgroup][step][thread] so that every access is one coalesced 8- or 16-byte word per lane;
+    // the register file cannot hold 16 steps of it besides the rest.  (F3 forms the right-hand side
+    // g_t again from its inputs, as F1 did, rather than keeping it here: fewer dirty lines in L2.)
     // B1 takes the last D products from registers (wl): their loads would be issued before F3
     // stores them.
     const __amdgpu_buffer_rsrc_t wrs = buf_rsrc(gptr(wsp) + (int64_t)blockIdx.x * SEG * blockDim.x,
@@ -366,14 +367,14 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const uint32_t vo = late(s.vb) + (uint32_t)j * (uint32_t)CB;
 #pragma unroll
         for (int c = 0; c < NCR; ++c) rk[u][c] = buf_ld16(s.col, vo + (uint32_t)(c * RP * 16), 0);
-        if constexpr (PK == 1) {
+        if constexpr (PK == 1 || PK == 3) {
             if (MODE == MODE_FWD) ra[u] = ioload(TI{}, rin, s.ro + colm1(s, j));
             else if (first) ra[u] = ioload(TO{}, ryo, (cmid - 1) * n + colm1(s, j));
         } else if constexpr (PK == 7) {
             if (MODE == MODE_BWD) ra[u] = ioload(TO{}, ryo, s.ro + colm1(s, j));
         }
         // B1 takes the last D forward products from registers (their loads would precede the stores)
-        if constexpr (PK == 3 || PK == 7) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
+        if constexpr (PK == 7) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
         else if constexpr (PK == 5) {
             if (j < SEG - D) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
         }
@@ -387,8 +388,8 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     for (int u = 0; u < D; ++u) { rg[u] = mk<T>(0, 0); wl[u] = mk<T>(0, 0); }
     CT carry = mk<T>(0, 0), xb = mk<T>(0, 0);
 
-    // one forward step: F1 (PK 1) builds g_t from the input and the previous layer row and stores it,
-    // F3 (PK 3) loads it back and stores w_t
+    // one forward step: F1 (PK 1) and F3 (PK 3) build g_t from the input and the previous layer row;
+    // F3 stores w_t
     // (full: the strip's rows are all outputs (front strip); wout: this lane's row is an output)
     auto fstep = [&](auto PKC, int j, auto UC, const Src& s, bool first, bool full, bool wout)
                      __attribute__((always_inline)) {
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         // reads as zero)
         const CT sE = ringscalar(std::integral_constant<int, XCOL_E>{}, u);
         CT g;
-        if constexpr (PK == 1) {
+        {
             const CT sL = ringscalar(std::integral_constant<int, MODE == MODE_FWD ? XCOL_APREV : XCOL_ANEXT>{}, u);
             const int c = colm1(s, j);
             if (MODE == MODE_FWD) {
@@ -412,9 +413,9 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
                 const CT yp = first ? ccast<T, double>(ra[u]) : ylr[c];
                 g = slot ? cmul<T>(sL, yp) : mk<T>(0, 0);
             }
-            buf_st(g, wrs, late(wlane), (uint32_t)j * wstep);
-        } else {
-            g = rg[u];
+            // g is rounded before the carry is added (no multiply-add across the two), so that F1 and
+            // F3 give it the same value
+            asm volatile("" : "+v"(g.x), "+v"(g.y));
         }
         const CT w = rowdot(cadd<T>(g, carry));
         const CT ne = cscale<T>(cmul<T>(sE, s.is2), (T)-1);
@@ -578,7 +579,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     Src sc = src_of(0), sn = src_of(1);
     phi_begin(0);
     prime(std::integral_constant<int, 1>{}, sc, true);
-    phase_f(std::integral_constant<int, 1>{}, sc, true, std::integral_constant<int, 3>{}, sc, false,
+    phase_f(std::integral_constant<int, 1>{}, sc, true, std::integral_constant<int, 3>{}, sc, true,
             [&](int pos) __attribute__((always_inline)) {
                 if ((pos & 1) == 0) phi_round(pos >> 1);
             });
@@ -589,7 +590,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     wg_barrier();
     for (int i = 0; i <= m; ++i) {
         carry = cv[sl * RP + r];
-        phase_f(std::integral_constant<int, 3>{}, sc, false, std::integral_constant<int, 5>{}, sc, false, no_hook);
+        phase_f(std::integral_constant<int, 3>{}, sc, i == 0, std::integral_constant<int, 5>{}, sc, false, no_hook);
         carry = mk<T>(0, 0);
         xb = mk<T>(0, 0);
         phase_b(std::integral_constant<int, 5>{}, sc, std::integral_constant<int, 7>{}, sc, false, no_hook);
