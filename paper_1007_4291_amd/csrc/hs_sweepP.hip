@@ -335,8 +335,10 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     // [workgroup][step][thread] so that every access is one coalesced 8- or 16-byte word per lane;
     // the register file cannot hold 16 steps of it besides the rest.  (F3 forms the right-hand side
     // g_t again from its inputs, as F1 did, rather than keeping it here: fewer dirty lines in L2.)
-    // B1 takes the last D products from registers (wl): their loads would be issued before F3
-    // stores them.
+    // The last D products stay in registers (wl) for B1, whose loads of them would be issued before F3
+    // stores them; in FP32 also for B3, and then they are not stored at all (fewer lines; in FP64 the
+    // registers are needed elsewhere).
+    constexpr bool WL3 = sizeof(T) == 4;
     const __amdgpu_buffer_rsrc_t wrs = buf_rsrc(gptr(wsp) + (int64_t)blockIdx.x * SEG * blockDim.x,
                                                 (uint32_t)(SEG * blockDim.x * sizeof(CT)));
     const uint32_t wlane = (uint32_t)(threadIdx.x * sizeof(CT));
@@ -374,9 +376,8 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
             if (MODE == MODE_BWD) ra[u] = ioload(TO{}, ryo, s.ro + colm1(s, j));
         }
         // B1 takes the last D forward products from registers (their loads would precede the stores)
-        if constexpr (PK == 7) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
-        else if constexpr (PK == 5) {
-            if (j < SEG - D) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
+        if constexpr (PK == 5 || PK == 7) {
+            if (j < SEG - D || (PK == 7 && !WL3)) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
         }
     };
     auto stage = [&](int u) __attribute__((always_inline)) {
@@ -420,7 +421,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const CT w = rowdot(cadd<T>(g, carry));
         const CT ne = cscale<T>(cmul<T>(sE, s.is2), (T)-1);
         if constexpr (PK == 3) {
-            buf_st(w, wrs, late(wlane), (uint32_t)j * wstep);
+            if (j < SEG - D || !WL3) buf_st(w, wrs, late(wlane), (uint32_t)j * wstep);
             if (j >= SEG - D) wl[u] = w;      // j - (SEG - D) == u
         }
         carry = csel<T>(valid, cmul<T>(ne, w), carry);
@@ -436,7 +437,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const CT sE = ringscalar(std::integral_constant<int, XCOL_E>{}, u);
         const CT v = rowdot(cmul<T>(s.is2, xb));
         CT wj = rg[u];
-        if constexpr (PK == 5) {
+        if (PK == 5 || WL3) {
             if (j >= SEG - D) wj = wl[D - 1 - u];   // j - (SEG - D) == D - 1 - u
         }
         const CT xn = cfms<T>(sE, v, wj);
