@@ -335,15 +335,18 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     // [workgroup][step][thread] so that every access is one coalesced 8- or 16-byte word per lane;
     // the register file cannot hold 16 steps of it besides the rest.  (F3 forms the right-hand side
     // g_t again from its inputs, as F1 did, rather than keeping it here: fewer dirty lines in L2.)
-    // The last D products stay in registers (wl) for B1, whose loads of them would be issued before F3
-    // stores them; in FP32 also for B3, and then they are not stored at all (fewer lines; in FP64 the
+    // The last KW products stay in registers (wl, by group of D steps) instead: in FP64 the last D,
+    // for B1, whose loads of them would be issued before F3 stores them (B3 loads all 16); in FP32
+    // the last 2 D, for B1 and B3, and then they are not stored at all (fewer lines; in FP64 the
     // registers are needed elsewhere).
     constexpr bool WL3 = sizeof(T) == 4;
+    constexpr int KW = WL3 ? 2 * D : D;
+    static_assert(KW <= SEG, "register-held products within one segment");
     const __amdgpu_buffer_rsrc_t wrs = buf_rsrc(gptr(wsp) + (int64_t)blockIdx.x * SEG * blockDim.x,
                                                 (uint32_t)(SEG * blockDim.x * sizeof(CT)));
     const uint32_t wlane = (uint32_t)(threadIdx.x * sizeof(CT));
     const uint32_t wstep = (uint32_t)(blockDim.x * sizeof(CT));
-    CT wl[D];
+    CT wl[2][D];
     // A column's coupling scalar (E, or the layer-row couplings), taken from the prefetch ring of the
     // lane that loaded it (a DPP row broadcast instead of an LDS read): entry PACK + W of the column
     // lies in chunk (PACK + W) * sizeof(CF) / 16, which lane chunk % RP holds as ring chunk chunk / RP.
@@ -377,7 +380,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         }
         // B1 takes the last D forward products from registers (their loads would precede the stores)
         if constexpr (PK == 5 || PK == 7) {
-            if (j < SEG - D || (PK == 7 && !WL3)) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
+            if (j < SEG - KW || (PK == 7 && !WL3)) buf_ld(rg[u], wrs, late(wlane), (uint32_t)j * wstep);
         }
     };
     auto stage = [&](int u) __attribute__((always_inline)) {
@@ -386,7 +389,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     };
 
 #pragma unroll
-    for (int u = 0; u < D; ++u) { rg[u] = mk<T>(0, 0); wl[u] = mk<T>(0, 0); }
+    for (int u = 0; u < D; ++u) { rg[u] = mk<T>(0, 0); wl[0][u] = mk<T>(0, 0); wl[1][u] = mk<T>(0, 0); }
     CT carry = mk<T>(0, 0), xb = mk<T>(0, 0);
 
     // one forward step: F1 (PK 1) and F3 (PK 3) build g_t from the input and the previous layer row;
@@ -421,8 +424,9 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const CT w = rowdot(cadd<T>(g, carry));
         const CT ne = cscale<T>(cmul<T>(sE, s.is2), (T)-1);
         if constexpr (PK == 3) {
-            if (j < SEG - D || !WL3) buf_st(w, wrs, late(wlane), (uint32_t)j * wstep);
-            if (j >= SEG - D) wl[u] = w;      // j - (SEG - D) == u
+            if (j < SEG - KW || !WL3) buf_st(w, wrs, late(wlane), (uint32_t)j * wstep);
+            if (j >= SEG - D) wl[1][u] = w;                     // j - (SEG - D) == u
+            else if (KW > D && j >= SEG - KW) wl[0][u] = w;     // j - (SEG - 2 D) == u
         }
         carry = csel<T>(valid, cmul<T>(ne, w), carry);
         wave_sync();
@@ -438,7 +442,8 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const CT v = rowdot(cmul<T>(s.is2, xb));
         CT wj = rg[u];
         if (PK == 5 || WL3) {
-            if (j >= SEG - D) wj = wl[D - 1 - u];   // j - (SEG - D) == D - 1 - u
+            if (j >= SEG - D) wj = wl[1][D - 1 - u];                     // j - (SEG - D) == D - 1 - u
+            else if (KW > D && j >= SEG - KW) wj = wl[0][D - 1 - u];     // j - (SEG - 2 D) == D - 1 - u
         }
         const CT xn = cfms<T>(sE, v, wj);
         xb = csel<T>(valid, xn, xb);
