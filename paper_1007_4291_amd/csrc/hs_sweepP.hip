@@ -344,8 +344,10 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     static_assert(KW <= SEG, "register-held products within one segment");
     const __amdgpu_buffer_rsrc_t wrs = buf_rsrc(gptr(wsp) + (int64_t)blockIdx.x * SEG * blockDim.x,
                                                 (uint32_t)(SEG * blockDim.x * sizeof(CT)));
-    const uint32_t wlane = (uint32_t)(threadIdx.x * sizeof(CT));
-    const uint32_t wstep = (uint32_t)(blockDim.x * sizeof(CT));
+    // Slots are packed to the rows that exist: row group g = wv * Q + q keeps row r at g * BS + r.  A
+    // padding lane (r >= BS) reads its group's first slot (its value is never used) and stores nothing.
+    const uint32_t wlane = (uint32_t)(((wv * Q + q) * BS + rr) * sizeof(CT));
+    const uint32_t wstep = (uint32_t)(nw * Q * BS * sizeof(CT));
     CT wl[2][D];
     // A column's coupling scalar (E, or the layer-row couplings), taken from the prefetch ring of the
     // lane that loaded it (a DPP row broadcast instead of an LDS read): entry PACK + W of the column
@@ -424,7 +426,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         const CT w = rowdot(cadd<T>(g, carry));
         const CT ne = cscale<T>(cmul<T>(sE, s.is2), (T)-1);
         if constexpr (PK == 3) {
-            if (j < SEG - KW || !WL3) buf_st(w, wrs, late(wlane), (uint32_t)j * wstep);
+            if ((j < SEG - KW || !WL3) && rok) buf_st(w, wrs, late(wlane), (uint32_t)j * wstep);
             if (j >= SEG - D) wl[1][u] = w;                     // j - (SEG - D) == u
             else if (KW > D && j >= SEG - KW) wl[0][u] = w;     // j - (SEG - 2 D) == u
         }
