@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0
 
 def parse():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--cpu-baseline-child", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -129,29 +130,30 @@ def copy_bandwidth(torch, gib=2):
     return nbytes / best / 1e9
 
 
-def sweep_bytes_flops(probs, B, fac_bytes, vin, vout):
-    """Algorithmic HBM bytes and flops of one forward-chain and one backward-chain launch.
+def sweep_bytes_flops(probs, B, fac_bytes, moving_only):
+    """Algorithmic HBM bytes and flops of one sweep-chain launch (one phase of M_alpha), as the method
+    defines them (whatever the kernel actually moves):
 
-    Factor: every B-row strip of both fronts is read twice per phase (the column-forward and the
-    column-backward pass of its block LU solve), n columns of B(B+1)/2 packed complex entries,
-    once per problem whatever the grouping of right-hand sides.  Vectors: per right-hand side, the
-    forward phase reads the input row and the neighbour's output row and writes the output row of
-    every moving layer, plus all rows of F and E; the backward phase reads the neighbour and own
-    output rows and writes the own row.  Flops: 2 passes x n columns x B^2 complex MACs (8 flops)
-    per strip per right-hand side.
+    * factor reads: every strip the launch solves is read twice per phase (the column-forward and the
+      column-backward pass of its block LU solve), n columns of B(B+1)/2 packed complex entries of the
+      factor precision, once per problem whatever the grouping of right-hand sides;
+    * vector I/O: an application reads f and writes u, 2 N R complex values of the factor precision,
+      half of it per phase;
+    * flops: 2 passes x n columns x B^2 complex multiply-adds (8 flops) per strip per right-hand side.
+
+    moving_only: the launch solves the moving layers only (the compressed chains; F and E run in their
+    own launch), L strips per problem instead of L + 2.
     """
     pack = B * (B + 1) // 2
-    b0 = b1 = fl = 0
+    by = fl = 0
     for p in probs:
         n, R = p.n, p.nrhs
         c = (n + 1) // 2 if n % 2 else n // 2 + 1
         L = (c - 1 - B) + (n - B - c)
-        strips = L + 2
-        fac = strips * 2 * n * pack * fac_bytes
-        b0 += fac + R * n * (2 * B * (vin + vout) + L * (vin + 2 * vout))
-        b1 += fac + R * n * (L * 3 * vout + 2 * (1 + 2 * B) * vout)
+        strips = L if moving_only else L + 2
+        by += strips * 2 * n * pack * fac_bytes + p.N * R * fac_bytes
         fl += R * strips * 2 * n * B * B * 8
-    return b0, b1, fl
+    return by, fl
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_chains_batched96_c64_traffic.json")
@@ -175,41 +177,117 @@ def measured_traffic(workload, prec_name, kind):
     return tr["traffic_bytes_per_launch"] if h.hexdigest() == tr.get("source_sha256") else None
 
 
-def cpu_baseline(probs):
-    """The oracle, untuned, on a bounded sample of the workload: whole problems with all their
-    right-hand sides -- the first two with n >= 255 (10-40 s of one core for the batched workload),
-    else the smallest problem.  Returns the record and [(problem, oracle solutions)]."""
-    import numpy as np
+def _oracle_system(task):
+    """One system of the sample, in a pool worker (one thread): assemble, factor (Algorithm 3, LAPACK
+    band LU per strip), FGMRES with the oracle's sweep (Algorithm 4) to the workload's tolerance.
+    Returns (task, factor seconds, solve seconds, iterations, solution)."""
     from threadpoolctl import threadpool_limits
 
+    import workloads as W
     from oracle import helmholtz as OH
     from oracle import krylov as OK
     from oracle import sweep as OS
-    by_n = sorted(probs, key=lambda q: q.n)
-    sample = [q for q in by_n if q.n >= 255][:2] or by_n[:1]
-    out, t = [], 0.0
+    workload, per_size, k, q = task
+    p = build_workload(workload, per_size)[0][k]
     with threadpool_limits(limits=1):
-        for p in sample:
-            op = OH.Params(n=p.n, omega=p.omega, alpha=p.alpha, pml_w=p.pml_w, mpml_w=p.mpml_w)
-            t0 = time.perf_counter()
-            Ao = OH.assemble(op, p.c)
-            Mo = OS.factor(op, p.c)
-            sols = []
-            for q in range(p.nrhs):
-                r = OK.fgmres(lambda v: Ao @ v, lambda v: OS.apply_sweep(Mo, v), p.f[q], p.restart, p.tol)
-                sols.append(r.x)
-            t += time.perf_counter() - t0
-            out.append((p, np.stack(sols)))
-    work = sum(p.nrhs * p.N for p in sample)
-    names = ", ".join(f"{p.name} (n={p.n}, {p.nrhs} RHS)" for p in sample)
-    p0 = sample[0]
-    return {"value": work / t, "unit": "RHS*N unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(sample)} problem(s): {names}; assemble + factor + FGMRES({p0.restart}) to {p0.tol:g}, "
-                      f"numpy/scipy FP64, 1 thread, {t:.1f} s"}, out
+        t0 = time.perf_counter()
+        op = OH.Params(n=p.n, omega=p.omega, alpha=p.alpha, pml_w=p.pml_w, mpml_w=p.mpml_w)
+        Ao = OH.assemble(op, p.c)
+        Mo = OS.factor(op, p.c)
+        t1 = time.perf_counter()
+        r = OK.fgmres(lambda v: Ao @ v, lambda v: OS.apply_sweep(Mo, v), p.f[q], p.restart, p.tol)
+        t2 = time.perf_counter()
+    return task, t1 - t0, t2 - t1, r.iters, r.x
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_child(workload, per_size):
+    """The oracle, untuned, on a bounded sample of the workload, in a process pool on the host cores
+    (run in a child process that never touches the GPU): one system (problem, right-hand side) per
+    worker -- for the batched workload one problem of each size class, two right-hand sides of the
+    n = 127 and n = 255 problems and one of the n = 511 problem (about 25 s of CPU work in all).
+    Prints one JSON record with the timings and the solutions."""
+    import multiprocessing as mp
+
+    import numpy as np
+    probs = build_workload(workload, per_size)[0]
+    tasks = []
+    for n in sorted(set(p.n for p in probs)):
+        k = [i for i, p in enumerate(probs) if p.n == n][0]
+        nq = 1 if (len(probs) > 1 and n >= 511) or len(probs) == 1 else 2
+        tasks += [(workload, per_size, k, q) for q in range(min(nq, probs[k].nrhs))]
+    cores = min(len(tasks), 16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(processes=cores) as pool:
+        res = pool.map(_oracle_system, tasks, chunksize=1)
+    wall = time.perf_counter() - t0
+    work = sum(probs[k].N for (_, _, k, _) in tasks)
+    cpu_s = sum(r[1] + r[2] for r in res)
+    # per-system single-core cost of each size class (factorisation once per problem, shared by its
+    # right-hand sides), extrapolated to the whole workload on all host cores
+    per_n = {}
+    for (task, tf, ts, it, _) in res:
+        p = probs[task[2]]
+        d = per_n.setdefault(p.n, {"factor_s": tf, "solve_s": [], "iters": []})
+        d["solve_s"].append(ts)
+        d["iters"].append(it)
+    t_one_core = 0.0
+    for p in probs:
+        d = per_n[p.n]
+        t_one_core += d["factor_s"] + p.nrhs * float(np.mean(d["solve_s"]))
+    ncpu = os.cpu_count() or 1
+    tot = sum(p.nrhs * p.N for p in probs)
+    rec = {"value": work / wall, "unit": "RHS*N unknowns/s", "cores": cores, "kind": "oracle",
+           "sample": (f"{len(tasks)} systems (" + ", ".join(f"n={probs[k].n} rhs {q}" for (_, _, k, q) in tasks)
+                      + f"), each assemble + factor + FGMRES({probs[0].restart}) to {probs[0].tol:g} in its own "
+                      f"process (numpy/scipy FP64, 1 thread each), {cores} processes in parallel: {wall:.1f} s wall, "
+                      f"{cpu_s:.1f} s CPU"),
+           "host": {"cpu_count": ncpu, "model": cpu_model()},
+           "per_size_single_core": {str(n): {"factor_s": round(d["factor_s"], 3),
+                                             "solve_s_per_rhs": round(float(np.mean(d["solve_s"])), 3),
+                                             "iters": d["iters"]} for n, d in sorted(per_n.items())},
+           "extrapolated_whole_workload_all_cores": {
+               "value": tot / (t_one_core / min(16, ncpu)), "cores": min(16, ncpu),
+               "note": "extrapolated: per-size single-core times x the workload's systems, divided over the cores"}}
+    sols = [{"k": task[2], "q": task[3], "re": np.real(x).tolist(), "im": np.imag(x).tolist()}
+            for (task, _, _, _, x) in res]
+    return rec, sols
+
+
+def cpu_baseline(workload, per_size):
+    """Run cpu_baseline_child in a fresh child process (the parent has initialised the GPU) and read its
+    record and solutions back."""
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        out = os.path.join(td, "cpu.json")
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", out, "--workload", workload,
+               "--per-size", str(per_size)]
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError(f"cpu baseline child failed: {r.stderr[-2000:]}")
+        with open(out) as fh:
+            d = json.load(fh)
+    return d["record"], d["solutions"]
 
 
 def main():
     a = parse()
+    if a.cpu_baseline_child:
+        rec, sols = cpu_baseline_child(a.workload, a.per_size)
+        with open(a.cpu_baseline_child, "w") as fh:
+            json.dump({"record": rec, "solutions": sols}, fh)
+        return 0
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         print("bench.py: only the one-GPU configuration exists (no multi-GPU path in this build)", file=sys.stderr)
@@ -239,24 +317,30 @@ def main():
     value = tot_unknowns / t_step
     u_main = [u.clone() for u in run.u]
 
-    # roofline of the dominant kernel: the sweep chain kernel (forward + backward launches)
+    # roofline of the dominant kernel: the sweep chain kernel (forward + backward launches); with the
+    # compressed chains the moving layers' kernel, timed apart from the front strips' launches
     fac_b = 8 if prec == hs.HELM_C64 else 16
-    b0, b1, fl = sweep_bytes_flops(probs, B, fac_b, 16, fac_b)
+    skind = schedule.get("kind", 1 if schedule.get("segmented") else 0)
+    bytes_per_launch, fl = sweep_bytes_flops(probs, B, fac_b, moving_only=(skind == 2))
     ms_f, n_f = ph["sweep_fwd"]
     ms_b, n_b = ph["sweep_bwd"]
     avg_ms = (ms_f + ms_b) / max(1, n_f + n_b)
-    bytes_per_launch = (b0 + b1) / 2
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    kind = f"segmented-{schedule.get('waves')}w" if schedule.get("segmented") else "plain"
+    kind = {0: "plain", 1: f"segmented-{schedule.get('waves')}w", 2: f"compressed-{schedule.get('ksplit')}rq"}[skind]
     traffic = measured_traffic(a.workload, a.prec, kind)
-    kname = (f"k_sweepP (segmented chains, {schedule.get('waves')}-wave workgroups)" if schedule.get("segmented")
-             else f"k_sweep{'2' if schedule.get('waves') == 2 else ''} (chains)") + " forward/backward launches"
+    kname = {0: f"k_sweep{'2' if schedule.get('waves') == 2 else ''} (chains)",
+             1: f"k_sweepP (segmented chains, {schedule.get('waves')}-wave workgroups)",
+             2: f"k_chainC (compressed moving-layer chains, {schedule.get('ksplit')} right-hand sides and "
+                f"{schedule.get('waves')} waves per workgroup)"}[skind] + " forward/backward launches"
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": int(traffic) if traffic else None,
             "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
             "launches": n_f + n_b, "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            "front_strips_ms_per_step": round(ph["sweep_front"][0] / a.steps, 3),
             "tflops": round(fl / (avg_ms * 1e-3) / 1e12, 4)}
     roof["frac_fp32_vector"] = round(roof["tflops"] / 157.3, 5)      # of the 157.3 TFLOP/s FP32 vector peak
+    roof["bytes_formula"] = ("per launch: sum over problems of (strips solved) x 2 passes x n x B(B+1)/2 x "
+                             f"{fac_b} B + N x R x {fac_b} B")
     hbm_meas = copy_bandwidth(torch)
     roof["measured_copy_gbs"] = round(hbm_meas, 1)
     roof["frac_of_measured_copy"] = round(achieved / hbm_meas, 5)
@@ -304,15 +388,15 @@ def main():
         del run64
 
     if not a.no_cpu_baseline:
-        cb, sols = cpu_baseline(probs)
+        cb, sols = cpu_baseline(a.workload, a.per_size)
         out["cpu_baseline"] = cb
         errs = []
-        for p, xs in sols:
-            k = [i for i, q in enumerate(probs) if q is p][0]
-            u_gpu = u_main[k].cpu().numpy()
-            errs += [np.linalg.norm(u_gpu[q] - xs[q]) / np.linalg.norm(xs[q]) for q in range(p.nrhs)]
-        out["max_rel_err_vs_oracle_sample"] = float(max(errs))
-        print(f"[bench] cpu baseline {cb['value']:.3e} RHS*N/s", file=sys.stderr, flush=True)
+        for d in sols:
+            x = np.asarray(d["re"]) + 1j * np.asarray(d["im"])
+            u_gpu = u_main[d["k"]].cpu().numpy()[d["q"]]
+            errs.append(float(np.linalg.norm(u_gpu - x) / np.linalg.norm(x)))
+        out["max_rel_err_vs_oracle_sample"] = max(errs)
+        print(f"[bench] cpu baseline {cb['value']:.3e} RHS*N/s on {cb['cores']} processes", file=sys.stderr, flush=True)
     print(json.dumps(out))
     return 0
 

@@ -64,6 +64,14 @@ typedef struct {
                              a subproblem strip has B = mpml_w + 1 rows                               */
     double pml_C;         /* PML strength C > 0 in sigma = (C/eta)((t-eta)/eta)^2 (eq. sigma)         */
     int32_t b_convention; /* 0: eta = (w+1)h, B = w+1 (default); 1: eta = w h, B = w                 */
+    int32_t layers_d;     /* grid rows eliminated per sweep step (end of Section 2.3); 0 or 1 = one
+                             row per step, the only form these kernels run: any other value returns
+                             HELM_EINVAL                                                              */
+    int32_t exact_mode;   /* 0: moving-PML subproblems (Section 2.2).  A non-zero value asks for the
+                             exact Schur complements (every subproblem the whole remaining block of
+                             A_alpha, Section 2.1), whose strips grow to n rows: the fixed-height strip
+                             kernels cannot hold them, so it returns HELM_EINVAL (the CPU reference
+                             implements that mode for testing)                                        */
 } helm_params;
 
 /* Library version string. */
@@ -201,10 +209,11 @@ int sweep_refactor_batch(helm_batch_t b, void* stream);
 
 /* Per-phase kernel timing with HIP events recorded on the launch stream around every kernel
  * group (process-wide; off by default).  Phases: 0 assemble, 1 factor, 2 sweep forward chains,
- * 3 sweep middle layer, 4 sweep backward chains, 5 matvec, 6 Krylov vector kernels.
- * helm_timing_read fills ms[7] (summed milliseconds) and launches[7] (kernel launches), waiting
+ * 3 sweep middle layer, 4 sweep backward chains, 5 matvec, 6 Krylov vector kernels, 7 the front
+ * strips F and E on their own (compressed chains only; otherwise inside 2 and 4).
+ * helm_timing_read fills ms[8] (summed milliseconds) and launches[8] (kernel launches), waiting
  * for the recorded events; reset != 0 clears the records. */
-#define HELM_NPHASES 7
+#define HELM_NPHASES 8
 int helm_timing_enable(int32_t on);
 int helm_timing_read(double* ms, int64_t* launches, int32_t reset);
 

@@ -73,13 +73,29 @@ struct DevBuf {
     template <class T> T* as() const { return (T*)p; }
 };
 
+// Size pre-check: fail with HELM_ENOMEM, before any allocation, when `need` bytes exceed the device
+// memory currently free (the allocations of one call would not fit).
+int precheck_bytes(double need, const char* what) {
+    size_t fr = 0, tot = 0;
+    hipError_t e = hipMemGetInfo(&fr, &tot);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HELM_EHIP, "hipMemGetInfo: %s", hipGetErrorString(e));
+    }
+    if (need > (double)fr)
+        return fail(HELM_ENOMEM, "%s needs %.3g GB of device memory, %.3g GB free (of %.3g GB)", what, need * 1e-9,
+                    (double)fr * 1e-9, (double)tot * 1e-9);
+    return HELM_OK;
+}
+
 bool supported_B(int B) { return B == 4 || B == 5 || B == 7 || B == 9 || B == 13 || B == 17; }
 
 constexpr int64_t kMaxN = 32767;
 
 // Per-phase kernel timing (process-wide, off by default): a start/stop event pair around each
 // kernel group, read back and summed on demand.
-enum Phase { PH_ASSEMBLE = 0, PH_FACTOR, PH_SWEEP_FWD, PH_SWEEP_MID, PH_SWEEP_BWD, PH_MATVEC, PH_KRYLOV, PH_N };
+enum Phase { PH_ASSEMBLE = 0, PH_FACTOR, PH_SWEEP_FWD, PH_SWEEP_MID, PH_SWEEP_BWD, PH_MATVEC, PH_KRYLOV, PH_SWEEP_FRONT,
+             PH_N };
 struct TimerRec { int phase; int launches; hipEvent_t a, b; };
 struct Timing {
     bool on = false;
@@ -127,6 +143,15 @@ struct helm_problem_s {
     ProbDev host{};
 };
 
+// Launch plan of a single-problem application for nrhs right-hand sides (host side): the plain chain
+// table (groups of Q right-hand sides per front), the middle table (Qm per wave), the segmented chain
+// table where the segmented sweep applies, and the workspace sizes.
+struct SoloPlan {
+    std::vector<ChainDev> ch, md, sc, cc;
+    int ks_chain = 1, ks_mid = 1, waves = 1, seg_wg = 0, kind = 0, cwaves = 0, crq = 8;
+    size_t spill_bytes = 0, segws_bytes = 0;
+};
+
 struct sweep_factors_s {
     helm_problem_t A = nullptr;
     int prec = 0;
@@ -136,12 +161,17 @@ struct sweep_factors_s {
     DevBuf prop, propw;
     int npropw = 0;
     bool seg = false;
+    // compressed moving-layer chains: per-segment blocks of every moving strip, their work table
+    // (comp: available), segment width
+    DevBuf cmp, compw;
+    int ncompw = 0, cseg = 0;
+    bool comp = false;
     std::vector<SubDev> hsubs;
     std::vector<int> sub_rows;
     // single-problem chain tables (rebuilt when nrhs changes)
-    DevBuf chains, mids, segch, segws;
-    int chains_nrhs = -1, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1, waves = 1;
-    int nsegch = 0, seg_wg = 0, kind = 0;   // kind 1: segmented chains
+    DevBuf chains, mids, segch, segws, cchains;
+    int chains_nrhs = -1, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1, waves = 1, ncch = 0, cwaves = 0, crq = 8;
+    int nsegch = 0, seg_wg = 0, kind = 0;   // kind 1: segmented chains, 2: compressed moving chains
     helm_batch_t solo = nullptr;    // cached batch of one for fgmres_solve
     int solo_nrhs = -1, solo_restart = -1;
     ~sweep_factors_s();
@@ -169,6 +199,11 @@ struct helm_batch_s {
     DevBuf propw, segch, segws;
     int npropw = 0, nsegch = 0, seg_wg = 0, seg_maxn = 0, kind = 0;
     bool seg = false;
+    // compressed moving chains (kind 2; F / E through the segmented kernel): compression work of all
+    // problems, chain table (problem, front, group of crq right-hand sides), waves per workgroup
+    DevBuf compw, cch;
+    int ncompw = 0, ncch = 0, cwaves = 0, crq = 8, cseg = 0;
+    bool comp = false;
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // graph form of FGMRES: a restart cycle captured once (on its own stream) as a few graphs that are
@@ -202,6 +237,12 @@ extern "C" const char* helm_last_error(void) { return g_err.c_str(); }
 static int check_params(const helm_params* p, int* Bout) {
     if (!p) return fail(HELM_EINVAL, "params is NULL");
     if (p->b_convention != 0 && p->b_convention != 1) return fail(HELM_EINVAL, "b_convention must be 0 or 1");
+    if (p->layers_d != 0 && p->layers_d != 1)
+        return fail(HELM_EINVAL, "layers_d=%d: only one grid row per sweep step (layers_d 0 or 1) is built",
+                    p->layers_d);
+    if (p->exact_mode != 0)
+        return fail(HELM_EINVAL, "exact_mode: exact Schur complements need strips of up to n rows; the strip "
+                                 "kernels hold at most 2B-1 rows");
     if (p->pml_w < 1 || p->mpml_w < 1) return fail(HELM_EINVAL, "pml_w and mpml_w must be >= 1");
     const int B = p->b_convention == 0 ? p->mpml_w + 1 : p->mpml_w;
     if (!supported_B(B)) return fail(HELM_EINVAL, "strip height B=%d not compiled (supported 4,5,7,9,13,17)", B);
@@ -327,6 +368,24 @@ static int seg_wg_target(int prec, int B, const std::vector<int>& n) {
     return t > wmin ? t : 0;
 }
 
+// Compressed moving chains: segment width (HELM_CSEG = 16 or 32; default 32), available when the
+// factors are complex64, the segmented kernel serves F / E, the strip height has an instance and a
+// strip's segments fit one workgroup (one wave each, at most 16).
+static int cseg_env() {
+    const char* e = std::getenv("HELM_CSEG");
+    const int v = e ? std::atoi(e) : 32;
+    return (v == 16 || v == 32) ? v : 32;
+}
+static bool comp_possible(int prec, bool seg, int B, int n, int cseg) {
+    return prec == HELM_C64 && seg && chainc_supported(B, cseg) && (n + cseg - 1) / cseg <= 16;
+}
+// HELM_SWEEP_KIND = 0 / 1 / 2 forces the plain / segmented / compressed chains for the single-problem
+// path and as the batch's starting schedule (unset: the best available, compressed first).
+static int kind_env() {
+    const char* e = std::getenv("HELM_SWEEP_KIND");
+    return e ? std::atoi(e) : -1;
+}
+
 // Run the a2 kernels for every strip of M's problem and check the pivots.
 static int factor_into(sweep_factors_t M, hipStream_t s) {
     helm_problem_t A = M->A;
@@ -335,7 +394,7 @@ static int factor_into(sweep_factors_t M, hipStream_t s) {
     const ProbDev* pd = A->pd.as<ProbDev>();
     (void)n;
     {
-        PhaseScope ph(PH_FACTOR, s, M->seg ? 3 : 2);
+        PhaseScope ph(PH_FACTOR, s, 2 + (M->seg ? 1 : 0) + (M->comp ? 1 : 0));
         if (!launch_factor(B, M->prec, pd, M->subs.as<SubDev>(), A->nsub - 1, M->status.as<int>(), s))
             return fail(HELM_EINVAL, "no factor kernel for B=%d", B);
         LAUNCHCHK();
@@ -345,6 +404,11 @@ static int factor_into(sweep_factors_t M, hipStream_t s) {
         if (M->seg) {
             if (!launch_prop(B, M->prec, pd, M->propw.as<PropDev>(), M->npropw, s))
                 return fail(HELM_EINVAL, "no propagator kernel for B=%d", B);
+            LAUNCHCHK();
+        }
+        if (M->comp) {
+            if (!launch_compress(B, M->cseg, M->prec == HELM_C128 ? 0 : 1, pd, M->compw.as<CompDev>(), M->ncompw, s))
+                return fail(HELM_EINVAL, "no compression kernel for B=%d, segment width %d", B, M->cseg);
             LAUNCHCHK();
         }
     }
@@ -370,6 +434,11 @@ extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_
     M->fac_elems = (int64_t)(A->nsub - 1) * n * pk + (int64_t)n * pkm;
     const size_t esz = prec == HELM_C128 ? sizeof(double2) : sizeof(float2);
     int rc;
+    {
+        // factor store plus, for the segmented sweep, one B x B propagator per 16 columns of every strip
+        const double props = (double)esz * (double)(A->nsub - 1) * (double)(((n + SEG - 1) / SEG) * B * B + 1);
+        if ((rc = precheck_bytes((double)esz * (double)M->fac_elems + props, "the factor store"))) return rc;
+    }
     if ((rc = M->fac.alloc(esz * (size_t)M->fac_elems))) return rc;
     // strip descriptors: F, lower layers, E, upper layers (all height B), then the middle (2B-1).
     // Consecutive layers of a front alternate their column direction; jprev / jnext are the layer
@@ -424,6 +493,30 @@ extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_
         if ((rc = M->propw.alloc(sizeof(PropDev) * pw.size()))) return rc;
         HIPCHK(hipMemcpy(M->propw.p, pw.data(), sizeof(PropDev) * pw.size(), hipMemcpyHostToDevice));
         M->npropw = (int)pw.size();
+    }
+    // compressed moving chains: one block per physical segment of every moving strip, strips in the
+    // order lower front (layers B+1 .. c-1), upper front (n-B .. c+1)
+    M->cseg = cseg_env();
+    M->comp = comp_possible(prec, M->seg, B, n, M->cseg);
+    if (M->comp) {
+        const int Sg = (n + M->cseg - 1) / M->cseg;
+        const int64_t blk = comp_block_elems(B, M->cseg);
+        const int nmov = A->L_lo + A->L_up;
+        if ((rc = precheck_bytes((double)sizeof(float2) * (double)blk * Sg * nmov, "the compressed strip blocks")))
+            return rc;
+        if ((rc = M->cmp.alloc(sizeof(float2) * (size_t)blk * Sg * nmov))) return rc;
+        std::vector<CompDev> cw;
+        for (int u = 0; u + 1 < A->nsub; ++u) {
+            if (u == 0 || u == A->L_lo + 1) continue;                 // F and E
+            const int k = u <= A->L_lo ? u - 1 : A->L_lo + (u - A->L_lo - 2);
+            for (int sg = 0; sg < Sg; ++sg)
+                cw.push_back(CompDev{0, S[u].cdir, S[u].rstep, sg, S[u].facp, S[u].ris2,
+                                     (char*)M->cmp.p + sizeof(float2) * (size_t)blk * ((size_t)k * Sg + sg)});
+        }
+        if ((rc = M->compw.alloc(sizeof(CompDev) * std::max<size_t>(1, cw.size())))) return rc;
+        if (!cw.empty())
+            HIPCHK(hipMemcpy(M->compw.p, cw.data(), sizeof(CompDev) * cw.size(), hipMemcpyHostToDevice));
+        M->ncompw = (int)cw.size();
     }
     if ((rc = factor_into(M.get(), s))) return rc;
     *out = M.release();
@@ -534,89 +627,176 @@ static std::vector<ChainDev> seg_table(const std::vector<int>& n, const std::vec
     return ch;
 }
 
-// Single-problem chain tables: groups of Q right-hand sides per front, Qm per middle wave.
-static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
+// Right-hand sides per compressed-chain workgroup (HELM_CRQ = 4 or 8; default 8).
+static int crq_env() {
+    const char* e = std::getenv("HELM_CRQ");
+    return (e && std::atoi(e) == 4) ? 4 : 8;
+}
+
+// Chain kernel kind: HELM_SWEEP_SEG = 0 / 1 forces the plain / segmented chains, HELM_SWEEP_KIND = 0 / 1 /
+// 2 the plain / segmented / compressed ones; unset, the compressed chains where available, else the
+// segmented ones, else the plain ones.  A forced kind that is not available falls back the same way.
+static int pick_kind(bool seg, bool comp) {
+    const int se = seg_env();
+    int k = se >= 0 ? (se == 0 ? 0 : 1) : kind_env();
+    if (k < 0) k = 2;
+    if (k == 2 && !comp) k = 1;
+    if (k == 1 && !seg) k = 0;
+    return k;
+}
+
+static SoloPlan solo_plan(const sweep_factors_t M, int nrhs) {
+    SoloPlan P;
     helm_problem_t A = M->A;
     const int n = A->n, B = A->B;
     int Q, Qm;
-    rhs_grouping(B, nrhs, &Q, &M->ks_chain, &Qm, &M->ks_mid);
-    M->waves = two_wave_chains(B) ? 2 : 1;
+    rhs_grouping(B, nrhs, &Q, &P.ks_chain, &Qm, &P.ks_mid);
+    P.waves = two_wave_chains(B) ? 2 : 1;
     const int groups = (nrhs + Q - 1) / Q, mgroups = (nrhs + Qm - 1) / Qm;
     const int64_t per = chain_spill_elems(n);
-    const size_t need = compute_elem(M->prec) * (size_t)per * (size_t)std::max(2 * groups, mgroups);
-    int rc;
-    if (M->spill.bytes < need) {
-        HIPCHK(hipStreamSynchronize(s));
-        if ((rc = M->spill.alloc(need))) return rc;
-    }
-    if (M->chains_nrhs == nrhs) return HELM_OK;
-    std::vector<ChainDev> ch, md;
+    P.spill_bytes = compute_elem(M->prec) * (size_t)per * (size_t)std::max(2 * groups, mgroups);
     for (int g = 0; g < groups; ++g)
         for (int f = 0; f < 2; ++f)
-            ch.push_back(ChainDev{0, f, g * Q, std::min(Q, nrhs - g * Q), g * Q, 0, (int64_t)ch.size() * per});
+            P.ch.push_back(ChainDev{0, f, g * Q, std::min(Q, nrhs - g * Q), g * Q, 0, (int64_t)P.ch.size() * per});
     for (int g = 0; g < mgroups; ++g)
-        md.push_back(ChainDev{0, 0, g * Qm, std::min(Qm, nrhs - g * Qm), g * Qm, 0, (int64_t)g * per});
-    HIPCHK(hipStreamSynchronize(s));
-    if ((rc = M->chains.alloc(sizeof(ChainDev) * ch.size()))) return rc;
-    if ((rc = M->mids.alloc(sizeof(ChainDev) * md.size()))) return rc;
-    HIPCHK(hipMemcpy(M->chains.p, ch.data(), sizeof(ChainDev) * ch.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(M->mids.p, md.data(), sizeof(ChainDev) * md.size(), hipMemcpyHostToDevice));
-    M->nchains = (int)ch.size();
-    M->nmids = (int)md.size();
-    M->kind = 0;
+        P.md.push_back(ChainDev{0, 0, g * Qm, std::min(Qm, nrhs - g * Qm), g * Qm, 0, (int64_t)g * per});
     if (M->seg) {
-        const std::vector<ChainDev> sc = seg_table({n}, {nrhs}, seg_wg_target(M->prec == HELM_C128 ? 0 : 1, B, {n}),
-                                                   &M->seg_wg);
-        if ((rc = M->segch.alloc(sizeof(ChainDev) * sc.size()))) return rc;
-        HIPCHK(hipMemcpy(M->segch.p, sc.data(), sizeof(ChainDev) * sc.size(), hipMemcpyHostToDevice));
-        M->nsegch = (int)sc.size();
-        const size_t wsb = compute_elem(M->prec) * (size_t)seg_ws_elems(M->nsegch, M->seg_wg);
-        if (M->segws.bytes < wsb && (rc = M->segws.alloc(wsb))) return rc;
-        M->kind = seg_env() == 0 ? 0 : 1;
+        P.sc = seg_table({n}, {nrhs}, seg_wg_target(M->prec == HELM_C128 ? 0 : 1, B, {n}), &P.seg_wg);
+        P.segws_bytes = compute_elem(M->prec) * (size_t)seg_ws_elems((int)P.sc.size(), P.seg_wg);
     }
+    if (M->comp) {
+        P.crq = crq_env();
+        P.cwaves = (n + M->cseg - 1) / M->cseg;
+        for (int g = 0; g * P.crq < nrhs; ++g)
+            for (int f = 0; f < 2; ++f)
+                P.cc.push_back(ChainDev{0, f, g * P.crq, std::min(P.crq, nrhs - g * P.crq), g * P.crq, 0, 0});
+    }
+    P.kind = pick_kind(M->seg, M->comp);
+    return P;
+}
+
+// Single-problem chain tables and workspaces of the factor handle, (re)built when nrhs changes.
+static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
+    const SoloPlan P = solo_plan(M, nrhs);
+    M->ks_chain = P.ks_chain;
+    M->ks_mid = P.ks_mid;
+    M->waves = P.waves;
+    int rc;
+    if (M->spill.bytes < P.spill_bytes) {
+        HIPCHK(hipStreamSynchronize(s));
+        if ((rc = M->spill.alloc(P.spill_bytes))) return rc;
+    }
+    if (M->chains_nrhs == nrhs) return HELM_OK;
+    HIPCHK(hipStreamSynchronize(s));
+    if ((rc = M->chains.alloc(sizeof(ChainDev) * P.ch.size()))) return rc;
+    if ((rc = M->mids.alloc(sizeof(ChainDev) * P.md.size()))) return rc;
+    HIPCHK(hipMemcpy(M->chains.p, P.ch.data(), sizeof(ChainDev) * P.ch.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(M->mids.p, P.md.data(), sizeof(ChainDev) * P.md.size(), hipMemcpyHostToDevice));
+    M->nchains = (int)P.ch.size();
+    M->nmids = (int)P.md.size();
+    if (M->seg) {
+        if ((rc = M->segch.alloc(sizeof(ChainDev) * P.sc.size()))) return rc;
+        HIPCHK(hipMemcpy(M->segch.p, P.sc.data(), sizeof(ChainDev) * P.sc.size(), hipMemcpyHostToDevice));
+        M->nsegch = (int)P.sc.size();
+        M->seg_wg = P.seg_wg;
+        if (M->segws.bytes < P.segws_bytes && (rc = M->segws.alloc(P.segws_bytes))) return rc;
+    }
+    if (M->comp) {
+        if ((rc = M->cchains.alloc(sizeof(ChainDev) * P.cc.size()))) return rc;
+        HIPCHK(hipMemcpy(M->cchains.p, P.cc.data(), sizeof(ChainDev) * P.cc.size(), hipMemcpyHostToDevice));
+        M->ncch = (int)P.cc.size();
+        M->cwaves = P.cwaves;
+        M->crq = P.crq;
+    }
+    M->kind = P.kind;
     M->chains_nrhs = nrhs;
     return HELM_OK;
 }
 
-extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nrhs, int32_t vec_prec, void* stream) {
-    if (!M || !f || !u) return fail(HELM_EINVAL, "NULL argument");
-    if (nrhs < 0) return fail(HELM_EINVAL, "nrhs < 0");
-    if (vec_prec != HELM_C128 && vec_prec != HELM_C64) return fail(HELM_EINVAL, "vec_prec must be HELM_C128 or HELM_C64");
-    if (M->prec == HELM_C128 && vec_prec != HELM_C128) return fail(HELM_EINVAL, "complex128 factors need complex128 vectors");
-    if (nrhs == 0) return HELM_OK;
-    hipStream_t s = (hipStream_t)stream;
-    int rc = ensure_solo_chains(M, nrhs, s);
-    if (rc) return rc;
+// Device operands of one single-problem application: tables and workspaces.
+struct SoloDev {
+    const ChainDev *ch, *md, *sc, *cc;
+    int nch, nmd, nsc, ncc, ks_chain, ks_mid, waves, seg_wg, kind, cwaves, crq;
+    void *spill, *segws;
+};
+
+static int solo_launch(const sweep_factors_t M, const SoloDev& D, const void* f, void* u, int vec_prec, hipStream_t s) {
     const ProbDev* pd = M->A->pd.as<ProbDev>();
-    IoDev io{f, u, M->fac.p, M->prop.p};
+    IoDev io{f, u, M->fac.p, M->prop.p, M->cmp.p};
     const int B = M->A->B;
+    if (D.kind == 2) {
+        PhaseScope ph(PH_SWEEP_FRONT, s);
+        if (!launch_chains_seg(B, M->prec, vec_prec, vec_prec, 0, pd, D.sc, D.nsc, nullptr, io, D.seg_wg, M->A->n, nullptr,
+                               D.segws, s, 1))
+            return fail(HELM_EINVAL, "no front-strip kernel for B=%d", B);
+        LAUNCHCHK();
+    }
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
-        const bool ok = M->kind == 1
-                            ? launch_chains_seg(B, M->prec, vec_prec, vec_prec, 0, pd, M->segch.as<ChainDev>(), M->nsegch,
-                                                nullptr, io, M->seg_wg, M->A->n, nullptr, M->segws.p, s)
-                            : run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 0, M->ks_chain, pd,
-                                         M->chains.as<ChainDev>(), M->nchains, nullptr, io, M->spill.p, nullptr, s);
-        if (!ok) return fail(HELM_EINVAL, "no sweep kernel for B=%d", B);
+        bool ok;
+        if (D.kind == 2)
+            ok = launch_chains_comp(B, M->cseg, D.crq, vec_prec, vec_prec, 0, pd, D.cc, D.ncc, nullptr, io, D.cwaves,
+                                    nullptr, s);
+        else if (D.kind == 1)
+            ok = launch_chains_seg(B, M->prec, vec_prec, vec_prec, 0, pd, D.sc, D.nsc, nullptr, io, D.seg_wg, M->A->n,
+                                   nullptr, D.segws, s);
+        else
+            ok = run_chains(D.waves, B, M->prec, vec_prec, vec_prec, 0, D.ks_chain, pd, D.ch, D.nch, nullptr, io, D.spill,
+                            nullptr, s);
+        if (!ok) return fail(HELM_EINVAL, "no sweep kernel for B=%d (kind %d)", B, D.kind);
         LAUNCHCHK();
     }
     {
         PhaseScope ph(PH_SWEEP_MID, s);
-        launch_middle(B, M->prec, vec_prec, vec_prec, M->ks_mid, pd, M->mids.as<ChainDev>(), M->nmids, nullptr, io,
-                      M->spill.p, nullptr, s);
+        if (!launch_middle(B, M->prec, vec_prec, vec_prec, D.ks_mid, pd, D.md, D.nmd, nullptr, io, D.spill, nullptr, s))
+            return fail(HELM_EINVAL, "no middle-strip kernel for height %d (factor precision %d, vectors %d)", 2 * B - 1,
+                        M->prec, vec_prec);
         LAUNCHCHK();
     }
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
-        if (M->kind == 1)
-            launch_chains_seg(B, M->prec, vec_prec, vec_prec, 1, pd, M->segch.as<ChainDev>(), M->nsegch, nullptr, io,
-                              M->seg_wg, M->A->n, nullptr, M->segws.p, s);
+        bool ok;
+        if (D.kind == 2)
+            ok = launch_chains_comp(B, M->cseg, D.crq, vec_prec, vec_prec, 1, pd, D.cc, D.ncc, nullptr, io, D.cwaves,
+                                    nullptr, s);
+        else if (D.kind == 1)
+            ok = launch_chains_seg(B, M->prec, vec_prec, vec_prec, 1, pd, D.sc, D.nsc, nullptr, io, D.seg_wg, M->A->n,
+                                   nullptr, D.segws, s);
         else
-            run_chains(M->waves, B, M->prec, vec_prec, vec_prec, 1, M->ks_chain, pd, M->chains.as<ChainDev>(), M->nchains,
-                       nullptr, io, M->spill.p, nullptr, s);
+            ok = run_chains(D.waves, B, M->prec, vec_prec, vec_prec, 1, D.ks_chain, pd, D.ch, D.nch, nullptr, io, D.spill,
+                            nullptr, s);
+        if (!ok)
+            return fail(HELM_EINVAL, "no backward sweep kernel for B=%d (factor precision %d, vectors %d, kind %d)", B,
+                        M->prec, vec_prec, D.kind);
+        LAUNCHCHK();
+    }
+    if (D.kind == 2) {
+        PhaseScope ph(PH_SWEEP_FRONT, s);
+        if (!launch_chains_seg(B, M->prec, vec_prec, vec_prec, 1, pd, D.sc, D.nsc, nullptr, io, D.seg_wg, M->A->n, nullptr,
+                               D.segws, s, 1))
+            return fail(HELM_EINVAL, "no front-strip kernel for B=%d", B);
         LAUNCHCHK();
     }
     return HELM_OK;
+}
+
+static int check_apply_args(sweep_factors_t M, const void* f, void* u, int32_t nrhs, int32_t vec_prec) {
+    if (!M || !f || !u) return fail(HELM_EINVAL, "NULL argument");
+    if (nrhs < 0) return fail(HELM_EINVAL, "nrhs < 0");
+    if (vec_prec != HELM_C128 && vec_prec != HELM_C64) return fail(HELM_EINVAL, "vec_prec must be HELM_C128 or HELM_C64");
+    if (M->prec == HELM_C128 && vec_prec != HELM_C128) return fail(HELM_EINVAL, "complex128 factors need complex128 vectors");
+    return HELM_OK;
+}
+
+extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nrhs, int32_t vec_prec, void* stream) {
+    int rc = check_apply_args(M, f, u, nrhs, vec_prec);
+    if (rc || nrhs == 0) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = ensure_solo_chains(M, nrhs, s))) return rc;
+    const SoloDev D{M->chains.as<ChainDev>(), M->mids.as<ChainDev>(), M->segch.as<ChainDev>(), M->cchains.as<ChainDev>(),
+                    M->nchains, M->nmids, M->nsegch, M->ncch, M->ks_chain, M->ks_mid, M->waves, M->seg_wg, M->kind,
+                    M->cwaves, M->crq, M->spill.p, M->segws.p};
+    return solo_launch(M, D, f, u, vec_prec, s);
 }
 
 extern "C" int sweep_subsolve(sweep_factors_t M, int32_t sub, const void* g, void* x, int32_t nrhs, void* stream) {
@@ -709,6 +889,31 @@ static int build_chain_tables(helm_batch_t b, int ks, int ksm) {
     return HELM_OK;
 }
 
+// Compressed chain table of a batch: one workgroup per (problem, front, group of crq right-hand sides),
+// problems in decreasing n (the longest chains start first); waves = segments of the largest problem.
+static int build_comp_table(helm_batch_t b, int crq) {
+    b->drop_graph();
+    const int count = b->count;
+    std::vector<int> order(count), base(count + 1, 0);
+    for (int p = 0; p < count; ++p) { order[p] = p; base[p + 1] = base[p] + b->nrhs[p]; }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->A[a]->n > b->A[c]->n; });
+    std::vector<ChainDev> cc;
+    int w = 1;
+    for (int p : order) {
+        w = std::max(w, (b->A[p]->n + b->cseg - 1) / b->cseg);
+        for (int g = 0; g * crq < b->nrhs[p]; ++g)
+            for (int f = 0; f < 2; ++f)
+                cc.push_back(ChainDev{p, f, g * crq, std::min(crq, b->nrhs[p] - g * crq), base[p] + g * crq, 0, 0});
+    }
+    int rc;
+    if ((rc = b->cch.alloc(sizeof(ChainDev) * cc.size()))) return rc;
+    HIPCHK(hipMemcpy(b->cch.p, cc.data(), sizeof(ChainDev) * cc.size(), hipMemcpyHostToDevice));
+    b->ncch = (int)cc.size();
+    b->cwaves = w;
+    b->crq = crq;
+    return HELM_OK;
+}
+
 extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t* M, const int32_t* nrhs, int32_t count,
                                  int32_t restart, void* stream, helm_batch_t* out) {
     if (!A || !M || !nrhs || !out) return fail(HELM_EINVAL, "NULL argument");
@@ -742,6 +947,9 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
         wo += (int64_t)b->nrhs[p] * b->N[p];
     }
     int rc;
+    if ((rc = precheck_bytes((double)sizeof(double2) * (double)(vo + wo) + (double)b->zelem * (double)zo,
+                             "the Krylov basis of the batch (V, Z, W)")))
+        return rc;
     if ((rc = b->V.alloc(sizeof(double2) * vo))) return rc;
     if ((rc = b->Z.alloc(b->zelem * zo))) return rc;
     if ((rc = b->W.alloc(sizeof(double2) * wo))) return rc;
@@ -806,9 +1014,27 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
             if ((rc = b->propw.alloc(sizeof(PropDev) * pw.size()))) return rc;
             HIPCHK(hipMemcpy(b->propw.p, pw.data(), sizeof(PropDev) * pw.size(), hipMemcpyHostToDevice));
             b->npropw = (int)pw.size();
-            b->kind = seg_env() == 0 ? 0 : 1;
         }
     }
+    // compressed moving chains: every member compressed with the same segment width
+    b->comp = b->seg;
+    b->cseg = M[0]->cseg;
+    for (int p = 0; p < count; ++p) b->comp = b->comp && M[p]->comp && M[p]->cseg == b->cseg;
+    if (b->comp) {
+        std::vector<CompDev> cw;
+        for (int p = 0; p < count; ++p) {
+            std::vector<CompDev> one(M[p]->ncompw);
+            if (!one.empty())
+                HIPCHK(hipMemcpy(one.data(), M[p]->compw.p, sizeof(CompDev) * one.size(), hipMemcpyDeviceToHost));
+            for (CompDev& d : one) { d.prob = p; cw.push_back(d); }
+        }
+        if ((rc = b->compw.alloc(sizeof(CompDev) * std::max<size_t>(1, cw.size())))) return rc;
+        if (!cw.empty())
+            HIPCHK(hipMemcpy(b->compw.p, cw.data(), sizeof(CompDev) * cw.size(), hipMemcpyHostToDevice));
+        b->ncompw = (int)cw.size();
+        if ((rc = build_comp_table(b.get(), crq_env()))) return rc;
+    }
+    b->kind = pick_kind(b->seg, b->comp);
     // io tables for V_j -> Z_j, and matvec tables Z_j -> W
     std::vector<IoDev> ios((size_t)kk * count);
     std::vector<MvDev> mvz((size_t)kk * count);
@@ -821,7 +1047,8 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
         for (int p = 0; p < count; ++p) {
             const int64_t blk = (int64_t)b->nrhs[p] * b->N[p];
             ios[(size_t)j * count + p] =
-                IoDev{V + b->voff[p] + j * blk, Z + b->zelem * (b->zoff[p] + j * blk), M[p]->fac.p, M[p]->prop.p};
+                IoDev{V + b->voff[p] + j * blk, Z + b->zelem * (b->zoff[p] + j * blk), M[p]->fac.p, M[p]->prop.p,
+                      M[p]->cmp.p};
             mvz[(size_t)j * count + p] = MvDev{Z + b->zelem * (b->zoff[p] + j * blk), W + b->woff[p], nullptr, b->nrhs[p],
                                                   sys0[p]};
         }
@@ -878,7 +1105,7 @@ extern "C" int sweep_refactor_batch(helm_batch_t b, void* stream) {
     const int B = b->B;
     HIPCHK(hipMemsetAsync(b->fstatus.p, 0, sizeof(int) * b->count, s));
     {
-        PhaseScope ph(PH_FACTOR, s, b->seg ? 3 : 2);
+        PhaseScope ph(PH_FACTOR, s, 2 + (b->seg ? 1 : 0) + (b->comp ? 1 : 0));
         // middles (few, long) on the side stream, overlapping the many height-B strips
         HIPCHK(hipEventRecord(b->ev_fork, s));
         HIPCHK(hipStreamWaitEvent(b->side, b->ev_fork, 0));
@@ -893,6 +1120,12 @@ extern "C" int sweep_refactor_batch(helm_batch_t b, void* stream) {
         if (b->seg) {
             if (!launch_prop(B, b->prec, b->probs.as<ProbDev>(), b->propw.as<PropDev>(), b->npropw, s))
                 return fail(HELM_EINVAL, "no propagator kernel for B=%d", B);
+            LAUNCHCHK();
+        }
+        if (b->comp) {
+            if (!launch_compress(B, b->cseg, b->prec == HELM_C128 ? 0 : 1, b->probs.as<ProbDev>(), b->compw.as<CompDev>(),
+                                 b->ncompw, s))
+                return fail(HELM_EINVAL, "no compression kernel for B=%d", B);
             LAUNCHCHK();
         }
         HIPCHK(hipStreamWaitEvent(s, b->ev_join, 0));
@@ -941,31 +1174,58 @@ extern "C" int helm_timing_read(double* ms, int64_t* launches, int32_t reset) {
 // device flags (nullptr: all); chains and middles whose systems are all inactive are skipped.
 static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int32_t* active, hipStream_t s) {
     const ProbDev* pd = b->probs.as<ProbDev>();
-    const IoDev none{nullptr, nullptr, nullptr};
+    const IoDev none{nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (b->kind == 2) {
+        PhaseScope ph(PH_SWEEP_FRONT, s);
+        if (!launch_chains_seg(b->B, b->prec, 0, out_prec, 0, pd, b->segch.as<ChainDev>(), b->nsegch, io, none, b->seg_wg,
+                               b->seg_maxn, active, b->segws.p, s, 1))
+            return fail(HELM_EINVAL, "no front-strip kernel for B=%d", b->B);
+        LAUNCHCHK();
+    }
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
-        const bool ok = b->kind == 1
-                            ? launch_chains_seg(b->B, b->prec, 0, out_prec, 0, pd, b->segch.as<ChainDev>(), b->nsegch, io,
-                                                none, b->seg_wg, b->seg_maxn, active, b->segws.p, s)
-                            : run_chains(b->waves, b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd,
-                                         b->chains.as<ChainDev>(), b->nchains, io, none, b->spill.p, active, s);
-        if (!ok) return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision", b->B);
+        bool ok;
+        if (b->kind == 2)
+            ok = launch_chains_comp(b->B, b->cseg, b->crq, 0, out_prec, 0, pd, b->cch.as<ChainDev>(), b->ncch, io, none,
+                                    b->cwaves, active, s);
+        else if (b->kind == 1)
+            ok = launch_chains_seg(b->B, b->prec, 0, out_prec, 0, pd, b->segch.as<ChainDev>(), b->nsegch, io, none,
+                                   b->seg_wg, b->seg_maxn, active, b->segws.p, s);
+        else
+            ok = run_chains(b->waves, b->B, b->prec, 0, out_prec, 0, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains,
+                            io, none, b->spill.p, active, s);
+        if (!ok) return fail(HELM_EINVAL, "no sweep kernel for B=%d / precision (kind %d)", b->B, b->kind);
         LAUNCHCHK();
     }
     {
         PhaseScope ph(PH_SWEEP_MID, s);
-        launch_middle(b->B, b->prec, 0, out_prec, b->ks_mid, pd, b->mids.as<ChainDev>(), b->nmids, io, none, b->spill.p,
-                      active, s);
+        if (!launch_middle(b->B, b->prec, 0, out_prec, b->ks_mid, pd, b->mids.as<ChainDev>(), b->nmids, io, none,
+                           b->spill.p, active, s))
+            return fail(HELM_EINVAL, "no middle-strip kernel for height %d (factor precision %d)", 2 * b->B - 1, b->prec);
         LAUNCHCHK();
     }
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
-        if (b->kind == 1)
-            launch_chains_seg(b->B, b->prec, 0, out_prec, 1, pd, b->segch.as<ChainDev>(), b->nsegch, io, none, b->seg_wg,
-                              b->seg_maxn, active, b->segws.p, s);
+        bool ok;
+        if (b->kind == 2)
+            ok = launch_chains_comp(b->B, b->cseg, b->crq, 0, out_prec, 1, pd, b->cch.as<ChainDev>(), b->ncch, io, none,
+                                    b->cwaves, active, s);
+        else if (b->kind == 1)
+            ok = launch_chains_seg(b->B, b->prec, 0, out_prec, 1, pd, b->segch.as<ChainDev>(), b->nsegch, io, none,
+                                   b->seg_wg, b->seg_maxn, active, b->segws.p, s);
         else
-            run_chains(b->waves, b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains, io,
-                       none, b->spill.p, active, s);
+            ok = run_chains(b->waves, b->B, b->prec, 0, out_prec, 1, b->ks_chain, pd, b->chains.as<ChainDev>(), b->nchains,
+                            io, none, b->spill.p, active, s);
+        if (!ok)
+            return fail(HELM_EINVAL, "no backward sweep kernel for B=%d (factor precision %d, kind %d)", b->B, b->prec,
+                        b->kind);
+        LAUNCHCHK();
+    }
+    if (b->kind == 2) {
+        PhaseScope ph(PH_SWEEP_FRONT, s);
+        if (!launch_chains_seg(b->B, b->prec, 0, out_prec, 1, pd, b->segch.as<ChainDev>(), b->nsegch, io, none, b->seg_wg,
+                               b->seg_maxn, active, b->segws.p, s, 1))
+            return fail(HELM_EINVAL, "no front-strip kernel for B=%d", b->B);
         LAUNCHCHK();
     }
     return HELM_OK;
@@ -1017,6 +1277,20 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
             if (per < best) { best = per; best_kind = 1; best_segt = t; }
         }
     }
+    int best_crq = b->crq;
+    if (b->comp && rc == HELM_OK) {
+        // compressed moving chains (F / E on the segmented kernel with its minimal workgroups) with 8 or 4
+        // right-hand sides per workgroup
+        if ((rc = build_seg_table(b, 0)) == HELM_OK) {
+            b->kind = 2;
+            for (int crq : {8, 4}) {
+                if ((rc = build_comp_table(b, crq))) break;
+                double per = 0;
+                if ((rc = time_one(&per))) break;
+                if (per < best) { best = per; best_kind = 2; best_crq = crq; best_segt = 0; }
+            }
+        }
+    }
     b->kind = 0;
     for (int w = (B <= 17 ? 2 : 1); w >= 1 && rc == HELM_OK; --w)
         for (int ks = 1; ks <= q && rc == HELM_OK; ks *= 2) {
@@ -1032,10 +1306,11 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
     if (rc) return rc;
     if ((rc = build_chain_tables(b, best_ks, ksm))) return rc;
     if (b->seg && (rc = build_seg_table(b, best_kind == 1 ? best_segt : 0))) return rc;
+    if (b->comp && (rc = build_comp_table(b, best_crq))) return rc;
     b->waves = best_w;
     b->kind = best_kind;
-    if (ksplit) *ksplit = best_kind == 1 ? 0 : best_ks;
-    if (waves) *waves = best_kind == 1 ? b->seg_wg : best_w;
+    if (ksplit) *ksplit = best_kind == 0 ? best_ks : (best_kind == 2 ? best_crq : 0);
+    if (waves) *waves = best_kind == 1 ? b->seg_wg : (best_kind == 2 ? b->cwaves : best_w);
     if (segmented) *segmented = best_kind;
     if (ms) *ms = best;
     return HELM_OK;
@@ -1047,7 +1322,7 @@ extern "C" int sweep_apply_batch(helm_batch_t b, const void* const* f, void* con
     std::vector<IoDev> io(b->count);
     for (int p = 0; p < b->count; ++p) {
         if (!f[p] || !u[p]) return fail(HELM_EINVAL, "NULL vector for problem %d", p);
-        io[p] = IoDev{f[p], u[p], b->M[p]->fac.p, b->M[p]->prop.p};
+        io[p] = IoDev{f[p], u[p], b->M[p]->fac.p, b->M[p]->prop.p, b->M[p]->cmp.p};
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemcpy(b->io_apply.p, io.data(), sizeof(IoDev) * b->count, hipMemcpyHostToDevice));

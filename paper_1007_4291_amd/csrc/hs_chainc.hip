@@ -1,0 +1,496 @@
+// a3 / a4 for the moving layers with every strip solve in compressed form.
+//
+// A moving layer's subproblem (Section 2.2) is only ever used as T~_m: input in its layer row, output
+// in its layer row (Algorithm 4: the diagonal applications and both substitutions touch T~_m g with g
+// placed in the layer row and read back from it).  Over one strip, T~_m is an n x n map whose
+// interaction between distant columns passes through the strip's B-row cross-section, so it is exactly
+// represented by per-segment operators of rank B (the structure of the block LU over the strip's
+// columns).  For physical segment s (SEG columns, local steps j in the strip's LU order), with the
+// strip's block LU recurrences
+//   forward:  z_t = e_slot gamma_t + c_t,  c_{t+1} = M_t z_t,         M_t = -E_t diag(1/s2) Lambda_t^{-1}
+//   backward: x_t = Lambda_t^{-1} z_t + N_t x_{t+1},  N_t = M_t^T      (Lambda_t^{-1} complex symmetric)
+// the segment maps its inputs (gamma on its columns, the carry c_in entering it, the value x_above
+// entering its backward pass) to its outputs (layer-row values y, carry out, value leaving backwards):
+//   c_out   = Phi c_in + QF gamma
+//   x_first = Phi^T x_above + W c_in + QB gamma
+//   y       = KS gamma + VS c_in + US x_above
+// Running the forward recurrence on the SEG + B unit inputs (gamma = e_j, c_in = e_k) gives
+// QF (carries of the gamma inputs at the end), Phi (carries of the c_in inputs), and, accumulating
+//   G = sum_t Z_t^T Lambda_t^{-1} Z_t      (Z_t: the z vectors of all unit inputs at step t)
+// over the segment, KS = G[gamma, gamma], QB = G[c, gamma], VS = G[gamma, c] = QB^T, W = G[c, c]; the
+// x_above response is the transpose of the forward one, US = QF^T (both follow from N_t = M_t^T).
+// k_compress forms these blocks in FP64 from the stored factors after every factorisation.
+//
+// The application of one strip is then, for all right-hand sides of a chain at once:
+//   1. per segment:   qf = QF gamma, qb = QB gamma, y = KS gamma
+//   2. forward spine: c_in of every segment, c_in(next) = Phi c_in + qf, in the strip's LU order
+//   3. per segment:   qb += W c_in, y += VS c_in
+//   4. backward spine: x_above(previous) = Phi^T x_above + qb, in reverse LU order
+//   5. per segment:   y += US x_above  -> the strip's layer-row output
+// the same operator as the sequential block solve (up to rounding), with a sequential depth of two
+// spines of n / SEG steps per strip instead of ~2n steps, and no per-column recurrence on the path.
+// F and E (full input and output) and the middle layer stay with the segmented / plain chain kernels.
+#include <algorithm>
+
+#include "hs_sweep_util.h"
+
+namespace hs {
+
+// Layout (complex elements) of the compressed block of one physical segment of one moving strip.
+template <int BS, int SEG> struct CompShape {
+    static constexpr int R1 = 2 * BS + SEG;          // rows of G1 = [QF; QB; KS], one column per gamma_j
+    static constexpr int R1P = (R1 + 15) & ~15;
+    static constexpr int R2 = BS + SEG;              // rows of G2 = [W; VS], one column per c_in entry
+    static constexpr int R2P = (R2 + 15) & ~15;
+    static constexpr int R3P = (SEG + 15) & ~15;     // rows of G3 = US, one column per x_above entry
+    static constexpr int O_G1 = 0;
+    static constexpr int O_G2 = O_G1 + SEG * R1P;
+    static constexpr int O_G3 = O_G2 + BS * R2P;
+    static constexpr int O_PHI = O_G3 + BS * R3P;    // Phi, row-major
+    static constexpr int O_PHIT = O_PHI + BS * BS;   // Phi^T, row-major
+    static constexpr int O_CPL = O_PHIT + BS * BS;   // [SEG][2]: layer-row couplings to the previous / next layer
+    static constexpr int SIZE = (O_CPL + 2 * SEG + 1) & ~1;
+};
+
+template <int BS, int SEG> __host__ __device__ constexpr bool comp_valid() {
+    return BS >= 2 && BS <= 16 && 2 * BS + SEG <= 64 && SEG % 16 == 0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// factor time: the compressed blocks
+// ---------------------------------------------------------------------------------------------
+constexpr int COMP_THREADS = 256;
+
+template <class TF, int BS, int SEG>
+__global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __restrict__ probs,
+                                                           const CompDev* __restrict__ work) {
+    using SH = CompShape<BS, SEG>;
+    constexpr int P = SEG + BS;                       // unit inputs: gamma_0..gamma_{SEG-1}, c_in e_0..e_{B-1}
+    constexpr int PACK = packed_size(BS), STRIDE = col_stride<TF>(BS);
+    constexpr int NZ = BS * P;
+    constexpr int NG = P * (P + 1) / 2;               // upper triangle of the symmetric G
+    constexpr int GPT = (NG + COMP_THREADS - 1) / COMP_THREADS;
+    constexpr int SLOT = BS - 1;                      // the layer row (local row order)
+    __shared__ double2 zs[BS][P];
+    __shared__ double2 ys[BS][P];
+    __shared__ double2 lam[BS][BS];
+    __shared__ double2 ne[BS];                        // -E_t / s2 of each row for the current step
+    __shared__ float2 cpl[SEG][2];
+    __shared__ float2 gram[P][P + 1];
+
+    const CompDev W = work[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int n = probs[W.prob].n;
+    const int tb = (W.cdir > 0) ? W.seg * SEG : n - W.seg * SEG - SEG;   // LU step of local step 0
+    const HS_GLOBAL C2<TF>* fac = gptr((const C2<TF>*)W.fac);
+
+    for (int e = tid; e < NZ; e += COMP_THREADS) {
+        const int r = e / P, p = e - (e / P) * P;
+        zs[r][p] = make_double2((p >= SEG && p - SEG == r) ? 1.0 : 0.0, 0.0);
+    }
+    for (int e = tid; e < 2 * SEG; e += COMP_THREADS) cpl[e >> 1][e & 1] = make_float2(0.f, 0.f);
+    int ga[GPT], gb[GPT];
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+        int g = tid + u * COMP_THREADS, a = 0;
+        if (g >= NG) g = NG - 1;
+        while (g >= P - a) { g -= P - a; ++a; }
+        ga[u] = a;
+        gb[u] = a + g;
+    }
+    double2 gacc[GPT];
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) gacc[u] = make_double2(0.0, 0.0);
+    // packed index -> (row, column) of this thread's entry of the stored column
+    int pr = 0, pk = 0;
+    if (tid < PACK) {
+        int e = tid;
+        while (e >= BS - pr) { e -= BS - pr; ++pr; }
+        pk = pr + e;
+    }
+    __syncthreads();
+
+    for (int j = 0; j < SEG; ++j) {
+        const int t = tb + j;
+        if (t < 0 || t >= n) continue;                 // columns past the strip's edge (uniform)
+        const HS_GLOBAL C2<TF>* col = fac + (int64_t)t * STRIDE;
+        if (tid < PACK) {
+            const C2<TF> v = gld(col + tid);
+            const double2 d = make_double2((double)v.x, (double)v.y);
+            lam[pr][pk] = d;
+            lam[pk][pr] = d;
+        } else if (tid < PACK + BS) {
+            const int r = tid - PACK;
+            const C2<TF> e = gld(col + PACK + XCOL_E);
+            const double2 is2 = gld(gptr(W.ris2 + W.rstep * r));
+            ne[r] = cscale<double>(cmul<double>(make_double2((double)e.x, (double)e.y), is2), -1.0);
+        } else if (tid == PACK + BS) {
+            const C2<TF> a = gld(col + PACK + XCOL_APREV), b = gld(col + PACK + XCOL_ANEXT);
+            cpl[j][0] = make_float2((float)a.x, (float)a.y);
+            cpl[j][1] = make_float2((float)b.x, (float)b.y);
+        }
+        if (tid == 0) zs[SLOT][j] = make_double2(1.0, 0.0);   // gamma_j enters at its own step
+        __syncthreads();
+        for (int e = tid; e < NZ; e += COMP_THREADS) {
+            const int r = e / P, p = e - (e / P) * P;
+            double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+            for (int k = 0; k < BS; ++k) acc = cfma<double>(lam[r][k], zs[k][p], acc);
+            ys[r][p] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < GPT; ++u) {
+            double2 acc = gacc[u];
+#pragma unroll 2
+            for (int r = 0; r < BS; ++r) acc = cfma<double>(zs[r][ga[u]], ys[r][gb[u]], acc);
+            gacc[u] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < NZ; e += COMP_THREADS) {
+            const int r = e / P, p = e - (e / P) * P;
+            zs[r][p] = cmul<double>(ne[r], ys[r][p]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+        if (tid + u * COMP_THREADS < NG) {
+            const float2 v = make_float2((float)gacc[u].x, (float)gacc[u].y);
+            gram[ga[u]][gb[u]] = v;
+            gram[gb[u]][ga[u]] = v;
+        }
+    }
+    __syncthreads();
+    HS_GLOBAL float2* out = gptr((float2*)W.out);
+    auto zf = [&](int r, int p) -> float2 { return make_float2((float)zs[r][p].x, (float)zs[r][p].y); };
+    const float2 zero = make_float2(0.f, 0.f);
+    for (int e = tid; e < SH::SIZE; e += COMP_THREADS) {
+        float2 v = zero;
+        if (e < SH::O_G2) {
+            const int j = e / SH::R1P, i = e - j * SH::R1P;
+            if (i < BS) v = zf(i, j);                                   // QF[i][j]
+            else if (i < 2 * BS) v = gram[SEG + i - BS][j];             // QB[i-B][j]
+            else if (i < SH::R1) v = gram[i - 2 * BS][j];               // KS[i-2B][j]
+        } else if (e < SH::O_G3) {
+            const int k = (e - SH::O_G2) / SH::R2P, i = (e - SH::O_G2) - k * SH::R2P;
+            if (i < BS) v = gram[SEG + i][SEG + k];                     // W[i][k]
+            else if (i < SH::R2) v = gram[i - BS][SEG + k];             // VS[i-B][k]
+        } else if (e < SH::O_PHI) {
+            const int k = (e - SH::O_G3) / SH::R3P, jj = (e - SH::O_G3) - k * SH::R3P;
+            if (jj < SEG) v = zf(k, jj);                                // US[jj][k] = QF[k][jj]
+        } else if (e < SH::O_PHIT) {
+            const int r = (e - SH::O_PHI) / BS, k = (e - SH::O_PHI) - r * BS;
+            v = zf(r, SEG + k);                                         // Phi[r][k]
+        } else if (e < SH::O_CPL) {
+            const int r = (e - SH::O_PHIT) / BS, k = (e - SH::O_PHIT) - r * BS;
+            v = zf(k, SEG + r);                                         // Phi^T[r][k]
+        } else if (e < SH::O_CPL + 2 * SEG) {
+            const int q = e - SH::O_CPL;
+            v = cpl[q >> 1][q & 1];
+        }
+        gst(out + e, v);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// application: one workgroup per chain (problem, front, group of RQ right-hand sides), one wave per
+// physical segment of the strips
+// ---------------------------------------------------------------------------------------------
+template <int BS, int SEG, int RQ> struct ChainCShape {
+    // LDS (complex64): gamma / layer row by segment and column, then per segment qf, qb, c_in, x_above
+    static constexpr int GAM = SEG * RQ;
+    static constexpr int VEC = BS * RQ;
+    static constexpr int PER_SEG = GAM + 4 * VEC;
+};
+
+template <int BS, int SEG, int MODE, class TI, class TO, int RQ>
+__global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
+                                                 const IoDev* __restrict__ io, IoDev io_val,
+                                                 const int32_t* __restrict__ active) {
+    static_assert(MODE == MODE_FWD || MODE == MODE_BWD, "compressed chains serve the front phases");
+    static_assert(comp_valid<BS, SEG>(), "one lane per row of the segment blocks");
+    using SH = CompShape<BS, SEG>;
+    using LS = ChainCShape<BS, SEG, RQ>;
+    extern __shared__ __align__(16) float2 lds[];
+    const int nwv = blockDim.x >> 6;
+    float2* const gam = lds;                           // [nwv][SEG][RQ]
+    float2* const qf = gam + nwv * LS::GAM;            // [nwv][BS][RQ]
+    float2* const qb = qf + nwv * LS::VEC;
+    float2* const cin = qb + nwv * LS::VEC;
+    float2* const xab = cin + nwv * LS::VEC;
+
+    const ChainDev ch = chains[blockIdx.x];
+    if (ch.nq == 0) return;
+    if (active && !any_active(active, ch)) return;
+    const ProbDev& P = probs[ch.prob];
+    const int n = P.n, cmid = P.c;
+    const int L = ch.front == 0 ? P.L_lo : P.L_up;
+    const int S = (n + SEG - 1) / SEG;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wv >= S) {
+        // no segment for this wave: take part in the chain's barriers, then leave
+        for (int b = 0; b < 4 * L; ++b) __syncthreads();
+        return;
+    }
+    const IoDev IO = io ? io[ch.prob] : io_val;
+    const int64_t N = (int64_t)n * n;
+    const int dirF = ch.front == 0 ? 1 : -1;
+    const int jF = ch.front == 0 ? BS : n + 1 - BS;
+    const int sbase = ch.front == 0 ? 0 : P.L_lo;      // compressed strips of the upper front follow the lower ones
+    const HS_GLOBAL float2* const cmp = gptr((const float2*)IO.cmp);
+    const HS_GLOBAL TI* const fin = gptr((const TI*)IO.in);
+    HS_GLOBAL TO* const uout = gptr((TO*)IO.out);
+    const int s = wv;
+    constexpr int NQH = 64 / SEG;                      // right-hand-side lanes per column in the input step
+    float2* const gs = gam + s * LS::GAM;
+
+    for (int i = 0; i < L; ++i) {
+        const int st = MODE == MODE_FWD ? i + 1 : L - i;      // strip index in its front (1..L)
+        const int jl = jF + dirF * st;                         // layer row
+        const int cd = (st & 1) ? -1 : 1;                      // column direction of its block LU
+        const HS_GLOBAL float2* const blk = cmp + ((int64_t)(sbase + st - 1) * S + s) * SH::SIZE;
+        // ---- 0. the strip's layer-row input on this segment's columns
+        {
+            const int cc = lane % SEG, qh = lane / SEG;
+            const int col = s * SEG + cc;
+            const int j = cd > 0 ? cc : SEG - 1 - cc;
+            const float2 a = gld(blk + SH::O_CPL + 2 * j + (MODE == MODE_FWD ? 0 : 1));
+#pragma unroll
+            for (int h = 0; h < RQ / NQH; ++h) {
+                const int q = qh + NQH * h;
+                float2 g = make_float2(0.f, 0.f);
+                if (col < n && q < ch.nq) {
+                    const int64_t rb = (int64_t)(ch.rhs0 + q) * N;
+                    if (MODE == MODE_FWD) {
+                        const double2 f = ld2(fin + rb + (int64_t)(jl - 1) * n + col);
+                        const float2 yp = i == 0 ? ccast<float, double>(ld2(uout + rb + (int64_t)(jl - dirF - 1) * n + col))
+                                                 : gs[cc * RQ + q];
+                        g = csub<float>(make_float2((float)f.x, (float)f.y), cmul<float>(a, yp));
+                    } else {
+                        const float2 yn = i == 0 ? ccast<float, double>(ld2(uout + rb + (int64_t)(cmid - 1) * n + col))
+                                                 : gs[cc * RQ + q];
+                        g = cmul<float>(a, yn);
+                    }
+                }
+                gs[cc * RQ + q] = g;
+            }
+        }
+        wave_sync();
+        // ---- 1. qf, qb and the local part of y from gamma
+        float2 yl[RQ];
+        {
+            float2 acc[RQ];
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) acc[q] = make_float2(0.f, 0.f);
+#pragma unroll 4
+            for (int j = 0; j < SEG; ++j) {
+                const float2 gcoef = gld(blk + SH::O_G1 + j * SH::R1P + (lane < SH::R1P ? lane : 0));
+                const int cc = cd > 0 ? j : SEG - 1 - j;
+#pragma unroll
+                for (int q = 0; q < RQ; ++q) acc[q] = cfma<float>(gcoef, gs[cc * RQ + q], acc[q]);
+            }
+            if (lane < BS) {
+#pragma unroll
+                for (int q = 0; q < RQ; ++q) qf[(s * BS + lane) * RQ + q] = acc[q];
+            } else if (lane < 2 * BS) {
+#pragma unroll
+                for (int q = 0; q < RQ; ++q) qb[(s * BS + lane - BS) * RQ + q] = acc[q];
+            }
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) yl[q] = acc[q];
+        }
+        __syncthreads();
+        // ---- 2. forward spine (wave 0): carries entering every segment, in the strip's LU order
+        const int sr = lane & 15, sq = lane >> 4, srr = sr < BS ? sr : BS - 1;
+        if (wv == 0) {
+            float2 c[RQ / 4];
+#pragma unroll
+            for (int h = 0; h < RQ / 4; ++h) c[h] = make_float2(0.f, 0.f);
+            for (int k = 0; k < S; ++k) {
+                const int ss = cd > 0 ? k : S - 1 - k;
+                const HS_GLOBAL float2* const pb = cmp + ((int64_t)(sbase + st - 1) * S + ss) * SH::SIZE + SH::O_PHI + srr * BS;
+                if (sr < BS) {
+#pragma unroll
+                    for (int h = 0; h < RQ / 4; ++h) cin[(ss * BS + sr) * RQ + sq + 4 * h] = c[h];
+                }
+                wave_sync();
+#pragma unroll
+                for (int h = 0; h < RQ / 4; ++h) c[h] = qf[(ss * BS + srr) * RQ + sq + 4 * h];
+#pragma unroll 4
+                for (int kk = 0; kk < BS; ++kk) {
+                    const float2 p = gld(pb + kk);
+#pragma unroll
+                    for (int h = 0; h < RQ / 4; ++h) c[h] = cfma<float>(p, cin[(ss * BS + kk) * RQ + sq + 4 * h], c[h]);
+                }
+                wave_sync();
+            }
+        }
+        __syncthreads();
+        // ---- 3. qb += W c_in, y += VS c_in
+        if (lane >= BS && lane < SH::R1) {
+            const int ii = lane - BS;
+            float2 acc[RQ];
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) acc[q] = make_float2(0.f, 0.f);
+#pragma unroll 4
+            for (int k = 0; k < BS; ++k) {
+                const float2 w = gld(blk + SH::O_G2 + k * SH::R2P + ii);
+#pragma unroll
+                for (int q = 0; q < RQ; ++q) acc[q] = cfma<float>(w, cin[(s * BS + k) * RQ + q], acc[q]);
+            }
+            if (lane < 2 * BS) {
+#pragma unroll
+                for (int q = 0; q < RQ; ++q) {
+                    float2* const d = &qb[(s * BS + lane - BS) * RQ + q];
+                    *d = cadd<float>(*d, acc[q]);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < RQ; ++q) yl[q] = cadd<float>(yl[q], acc[q]);
+            }
+        }
+        __syncthreads();
+        // ---- 4. backward spine (wave 0): values entering every segment from above, reverse LU order
+        if (wv == 0) {
+            float2 x[RQ / 4];
+#pragma unroll
+            for (int h = 0; h < RQ / 4; ++h) x[h] = make_float2(0.f, 0.f);
+            for (int k = 0; k < S; ++k) {
+                const int ss = cd > 0 ? S - 1 - k : k;
+                const HS_GLOBAL float2* const pb = cmp + ((int64_t)(sbase + st - 1) * S + ss) * SH::SIZE + SH::O_PHIT + srr * BS;
+                if (sr < BS) {
+#pragma unroll
+                    for (int h = 0; h < RQ / 4; ++h) xab[(ss * BS + sr) * RQ + sq + 4 * h] = x[h];
+                }
+                wave_sync();
+#pragma unroll
+                for (int h = 0; h < RQ / 4; ++h) x[h] = qb[(ss * BS + srr) * RQ + sq + 4 * h];
+#pragma unroll 4
+                for (int kk = 0; kk < BS; ++kk) {
+                    const float2 p = gld(pb + kk);
+#pragma unroll
+                    for (int h = 0; h < RQ / 4; ++h) x[h] = cfma<float>(p, xab[(ss * BS + kk) * RQ + sq + 4 * h], x[h]);
+                }
+                wave_sync();
+            }
+        }
+        __syncthreads();
+        // ---- 5. y += US x_above; the strip's layer-row output
+        if (lane >= 2 * BS && lane < SH::R1) {
+            const int jj = lane - 2 * BS;
+#pragma unroll 4
+            for (int k = 0; k < BS; ++k) {
+                const float2 us = gld(blk + SH::O_G3 + k * SH::R3P + jj);
+#pragma unroll
+                for (int q = 0; q < RQ; ++q) yl[q] = cfma<float>(us, xab[(s * BS + k) * RQ + q], yl[q]);
+            }
+            const int cc = cd > 0 ? jj : SEG - 1 - jj;
+            const int col = s * SEG + cc;
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) {
+                float2 y = yl[q];
+                if (col < n && q < ch.nq) {
+                    HS_GLOBAL TO* const dst = uout + (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col;
+                    if (MODE == MODE_BWD) y = csub<float>(ccast<float, double>(ld2(dst)), y);
+                    gst(dst, cvt_out<TO, float>(y));
+                }
+                gs[cc * RQ + q] = y;
+            }
+        }
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------------------------
+bool chainc_supported(int B, int seg) {
+    if (seg == 32) return B == 4 || B == 5 || B == 7 || B == 9 || B == 13;
+    if (seg == 16) return B == 4 || B == 5 || B == 7 || B == 9 || B == 13;
+    return false;
+}
+
+int64_t comp_block_elems(int B, int seg) {
+#define HS_CASE(BV, SV) \
+    if (B == BV && seg == SV) return CompShape<BV, SV>::SIZE;
+    HS_CASE(4, 16) HS_CASE(5, 16) HS_CASE(7, 16) HS_CASE(9, 16) HS_CASE(13, 16)
+    HS_CASE(4, 32) HS_CASE(5, 32) HS_CASE(7, 32) HS_CASE(9, 32) HS_CASE(13, 32)
+#undef HS_CASE
+    return 0;
+}
+
+template <class TF, int SEG>
+static bool compress_typed(int B, const ProbDev* probs, const CompDev* work, int nwork, hipStream_t s) {
+    switch (B) {
+#define HS_CASE(BV) \
+    case BV: hipLaunchKernelGGL((k_compress<TF, BV, SEG>), dim3(nwork), dim3(COMP_THREADS), 0, s, probs, work); return true;
+        HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13)
+#undef HS_CASE
+        default: return false;
+    }
+}
+
+bool launch_compress(int B, int seg, int prec, const ProbDev* probs, const CompDev* work, int nwork, hipStream_t s) {
+    if (nwork <= 0) return true;
+    if (!chainc_supported(B, seg)) return false;
+    if (prec == 0) return seg == 32 ? compress_typed<double, 32>(B, probs, work, nwork, s)
+                                    : compress_typed<double, 16>(B, probs, work, nwork, s);
+    return seg == 32 ? compress_typed<float, 32>(B, probs, work, nwork, s)
+                     : compress_typed<float, 16>(B, probs, work, nwork, s);
+}
+
+size_t chainc_lds_bytes(int B, int seg, int rq, int waves) {
+    const int per = seg * rq + 4 * B * rq;
+    return (size_t)per * waves * sizeof(float2);
+}
+
+template <int BS, int SEG, int MODE, class TI, class TO, int RQ>
+static void chainc_go(const ProbDev* probs, const ChainDev* chains, int nch, const IoDev* io, IoDev iov, int waves,
+                      const int32_t* act, hipStream_t s) {
+    const size_t lds = chainc_lds_bytes(BS, SEG, RQ, waves);
+    hipLaunchKernelGGL((k_chainC<BS, SEG, MODE, TI, TO, RQ>), dim3(nch), dim3(64 * waves), lds, s, probs, chains, io, iov,
+                       act);
+}
+
+template <int SEG, int MODE, class TI, class TO, int RQ>
+static bool chainc_b(int B, const ProbDev* probs, const ChainDev* chains, int nch, const IoDev* io, IoDev iov, int waves,
+                     const int32_t* act, hipStream_t s) {
+    switch (B) {
+#define HS_CASE(BV) \
+    case BV: chainc_go<BV, SEG, MODE, TI, TO, RQ>(probs, chains, nch, io, iov, waves, act, s); return true;
+        HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13)
+#undef HS_CASE
+        default: return false;
+    }
+}
+
+template <int MODE, class TI, class TO>
+static bool chainc_r(int B, int seg, int rq, const ProbDev* probs, const ChainDev* chains, int nch, const IoDev* io,
+                     IoDev iov, int waves, const int32_t* act, hipStream_t s) {
+    if (seg == 32 && rq == 8) return chainc_b<32, MODE, TI, TO, 8>(B, probs, chains, nch, io, iov, waves, act, s);
+    if (seg == 32 && rq == 4) return chainc_b<32, MODE, TI, TO, 4>(B, probs, chains, nch, io, iov, waves, act, s);
+    if (seg == 16 && rq == 8) return chainc_b<16, MODE, TI, TO, 8>(B, probs, chains, nch, io, iov, waves, act, s);
+    if (seg == 16 && rq == 4) return chainc_b<16, MODE, TI, TO, 4>(B, probs, chains, nch, io, iov, waves, act, s);
+    return false;
+}
+
+bool launch_chains_comp(int B, int seg, int rq, int in_prec, int out_prec, int phase, const ProbDev* probs,
+                        const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves,
+                        const int32_t* active, hipStream_t s) {
+    if (nchains <= 0) return true;
+    if (!chainc_supported(B, seg) || waves < 1 || waves > 16) return false;
+    if (chainc_lds_bytes(B, seg, rq, waves) > 160 * 1024) return false;
+    if (in_prec == 0 && out_prec == 0)
+        return phase == 0 ? chainc_r<MODE_FWD, double2, double2>(B, seg, rq, probs, chains, nchains, io, io_val, waves, active, s)
+                          : chainc_r<MODE_BWD, double2, double2>(B, seg, rq, probs, chains, nchains, io, io_val, waves, active, s);
+    if (in_prec == 0 && out_prec == 1)
+        return phase == 0 ? chainc_r<MODE_FWD, double2, float2>(B, seg, rq, probs, chains, nchains, io, io_val, waves, active, s)
+                          : chainc_r<MODE_BWD, double2, float2>(B, seg, rq, probs, chains, nchains, io, io_val, waves, active, s);
+    if (in_prec == 1 && out_prec == 1)
+        return phase == 0 ? chainc_r<MODE_FWD, float2, float2>(B, seg, rq, probs, chains, nchains, io, io_val, waves, active, s)
+                          : chainc_r<MODE_BWD, float2, float2>(B, seg, rq, probs, chains, nchains, io, io_val, waves, active, s);
+    return false;
+}
+
+}  // namespace hs

@@ -157,6 +157,7 @@ struct IoDev {
     void* out;
     const void* fac;    // factor store of the problem (complex elements of the factor precision)
     const void* prop;   // segment propagators of the problem's front strips (segmented sweep), or nullptr
+    const void* cmp;    // compressed blocks of the problem's moving strips (compressed chains), or nullptr
 };
 
 // Columns per segment of the segmented strip solves.
@@ -171,6 +172,17 @@ struct PropDev {
     const void* fac;        // first stored column of the strip
     const double2* ris2;
     void* out;              // the strip's propagators: [segment][row-major BS x BS block]
+};
+
+// One compression work item: one physical segment of one moving strip (k_compress).
+struct CompDev {
+    int32_t prob;           // index into the ProbDev table
+    int32_t cdir;           // column direction of the strip's block LU
+    int32_t rstep;          // 1/s2 of local row r at ris2[rstep * r]
+    int32_t seg;            // physical segment (columns seg*SEG .. seg*SEG+SEG-1)
+    const void* fac;        // first stored column of the strip
+    const double2* ris2;
+    void* out;              // the segment's compressed block
 };
 
 __host__ __device__ constexpr int packed_size(int bs) { return bs * (bs + 1) / 2; }

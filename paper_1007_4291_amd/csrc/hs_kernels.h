@@ -74,9 +74,10 @@ bool launch_chains2(int B, int prec, int in_prec, int out_prec, int phase, int k
 // for strip heights without an instance or a workgroup beyond the LDS.  max_n: the largest n of
 // the problems in the table (sizes the shared propagator area).
 // ws: workspace of seg_ws_elems(nchains, waves) complex elements of the compute precision.
+// only_front != 0: the front strips (F, E) alone (the moving layers applied by the compressed chains).
 bool launch_chains_seg(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
                        const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves, int max_n,
-                       const int32_t* active, void* ws, hipStream_t s);
+                       const int32_t* active, void* ws, hipStream_t s, int only_front = 0);
 int64_t seg_ws_elems(int nchains, int waves);
 bool seg_supported(int B);
 // LDS of a segmented workgroup of `waves` waves for problems up to max_n, and whether it fits.
@@ -173,5 +174,20 @@ void launch_iter_flags(int nsys, int j, const double* est, const double* fnorm, 
                        int32_t* cnt, int32_t* active, hipStream_t s);
 // a[0..n) = 0 (a kernel, so that it may sit inside a captured graph)
 void launch_zero_i32(int32_t* a, int n, hipStream_t s);
+
+// Compressed moving-layer chains (layer-row-to-layer-row strip maps, precomputed per segment of SEG
+// columns): available strip heights for a segment width, complex elements of one segment's block.
+bool chainc_supported(int B, int seg);
+int64_t comp_block_elems(int B, int seg);
+// Compressed blocks of the segments listed in `work` from the stored factors (prec 0: complex128
+// factors, 1: complex64); blocks are stored in complex64.
+bool launch_compress(int B, int seg, int prec, const ProbDev* probs, const CompDev* work, int nwork, hipStream_t s);
+// One workgroup per chain (problem, front, up to rq right-hand sides), `waves` waves (one per segment
+// of the largest problem, <= 16); io[p].cmp holds problem p's blocks.  Moving layers only: F / E and the
+// middle layer are applied by the other kernels.  Returns false for unsupported shapes.
+bool launch_chains_comp(int B, int seg, int rq, int in_prec, int out_prec, int phase, const ProbDev* probs,
+                        const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves,
+                        const int32_t* active, hipStream_t s);
+size_t chainc_lds_bytes(int B, int seg, int rq, int waves);
 
 }  // namespace hs

@@ -160,7 +160,8 @@ template <class T> struct SegWaves { static constexpr int MAX = sizeof(T) == 8 ?
 template <class T, class TF, class TI, class TO, int BS, int MODE>
 __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
                                                  const IoDev* __restrict__ io, IoDev io_val,
-                                                 const int32_t* __restrict__ active, C2<T>* __restrict__ wsp) {
+                                                 const int32_t* __restrict__ active, C2<T>* __restrict__ wsp,
+                                                 int only_front) {
     static_assert(MODE == MODE_FWD || MODE == MODE_BWD, "segmented chains serve the front phases");
     using CT = C2<T>;
     using CF = C2<TF>;
@@ -190,7 +191,8 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
     if (active && !any_active(active, ch)) return;               // whole workgroup
     const ProbDev& P = probs[ch.prob];
     const int n = P.n, B = P.B, cmid = P.c;
-    const int L = ch.front == 0 ? P.L_lo : P.L_up;
+    // only_front: the front strip (F or E) alone, the moving layers being applied by another kernel
+    const int L = only_front ? 0 : (ch.front == 0 ? P.L_lo : P.L_up);
     const int m = L;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane % RP, q = lane / RP;
     const int Wr = ch.wrhs;                    // waves per right-hand side
@@ -225,6 +227,9 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
 
     const int dirF = ch.front == 0 ? 1 : -1;
     const int jF = ch.front == 0 ? B : n + 1 - B;
+    // backward phase: the row whose updated values feed the first strip's layer row (the middle
+    // layer, or the first moving layer when the front strip runs alone)
+    const int jfirst = only_front ? jF + dirF : cmid;
     auto strip_t = [&](int i) __attribute__((always_inline)) { return MODE == MODE_FWD ? i : L - i; };
     auto strip_dir = [&](int i) __attribute__((always_inline)) -> int { return (strip_t(i) & 1) ? -1 : 1; };
     auto strip_row = [&](int i) __attribute__((always_inline)) -> int {
@@ -376,7 +381,7 @@ __global__ __launch_bounds__(64 * SegWaves<T>::MAX) void k_sweepP(const ProbDev*
         for (int c = 0; c < NCR; ++c) rk[u][c] = buf_ld16(s.col, vo + (uint32_t)(c * RP * 16), 0);
         if constexpr (PK == 1 || PK == 3) {
             if (MODE == MODE_FWD) ra[u] = ioload(TI{}, rin, s.ro + colm1(s, j));
-            else if (first) ra[u] = ioload(TO{}, ryo, (cmid - 1) * n + colm1(s, j));
+            else if (first) ra[u] = ioload(TO{}, ryo, (jfirst - 1) * n + colm1(s, j));
         } else if constexpr (PK == 7) {
             if (MODE == MODE_BWD) ra[u] = ioload(TO{}, ryo, s.ro + colm1(s, j));
         }
@@ -661,19 +666,19 @@ bool seg_fits(int prec, int B, int waves, int max_n) {
 
 template <class T, class TF, class TI, class TO, int BV, int MODE>
 static bool segp_launch(const ProbDev* probs, const ChainDev* chains, int nb, const IoDev* io, IoDev iov, int waves,
-                        const int32_t* act, void* ws, size_t lds, hipStream_t s) {
+                        const int32_t* act, void* ws, size_t lds, int only_front, hipStream_t s) {
     if (lds > 160 * 1024) return false;
     hipLaunchKernelGGL((k_sweepP<T, TF, TI, TO, BV, MODE>), dim3(nb), dim3(64 * waves), lds, s, probs, chains, io, iov, act,
-                       (C2<T>*)ws);
+                       (C2<T>*)ws, only_front);
     return true;
 }
 
 template <class T, class TF, class TI, class TO, int MODE>
 static bool segp_typed(int bs, const ProbDev* probs, const ChainDev* chains, int nb, const IoDev* io, IoDev iov,
-                       int waves, const int32_t* act, void* ws, size_t lds, hipStream_t s) {
+                       int waves, const int32_t* act, void* ws, size_t lds, int of, hipStream_t s) {
     switch (bs) {
 #define HS_CASE(BV) \
-    case BV: return segp_launch<T, TF, TI, TO, BV, MODE>(probs, chains, nb, io, iov, waves, act, ws, lds, s);
+    case BV: return segp_launch<T, TF, TI, TO, BV, MODE>(probs, chains, nb, io, iov, waves, act, ws, lds, of, s);
         HS_CASE(4) HS_CASE(5) HS_CASE(7) HS_CASE(9) HS_CASE(13)
 #undef HS_CASE
         default: return false;
@@ -682,32 +687,32 @@ static bool segp_typed(int bs, const ProbDev* probs, const ChainDev* chains, int
 
 template <int MODE>
 static bool segp_prec(int bs, int prec, int in_prec, int out_prec, const ProbDev* probs, const ChainDev* chains, int nb,
-                      const IoDev* io, IoDev iov, int waves, const int32_t* act, void* ws, size_t lds, hipStream_t s) {
+                      const IoDev* io, IoDev iov, int waves, const int32_t* act, void* ws, size_t lds, int of, hipStream_t s) {
     if (prec == 0) {
         if (in_prec == 0 && out_prec == 0)
             return segp_typed<double, double, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds,
-                                                                      s);
+                                                                      of, s);
         return false;
     }
     if (in_prec == 0 && out_prec == 0)
-        return segp_typed<float, float, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds, s);
+        return segp_typed<float, float, double2, double2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds, of, s);
     if (in_prec == 0 && out_prec == 1)
-        return segp_typed<float, float, double2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds, s);
+        return segp_typed<float, float, double2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds, of, s);
     if (in_prec == 1 && out_prec == 1)
-        return segp_typed<float, float, float2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds, s);
+        return segp_typed<float, float, float2, float2, MODE>(bs, probs, chains, nb, io, iov, waves, act, ws, lds, of, s);
     return false;
 }
 
 bool launch_chains_seg(int B, int prec, int in_prec, int out_prec, int phase, const ProbDev* probs,
                        const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves, int max_n,
-                       const int32_t* active, void* ws, hipStream_t s) {
+                       const int32_t* active, void* ws, hipStream_t s, int only_front) {
     if (nchains <= 0) return true;
     if (!seg_fits(prec, B, waves, max_n)) return false;
     const size_t lds = seg_lds_bytes(prec, B, waves, max_n);
     return phase == 0 ? segp_prec<MODE_FWD>(B, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, waves, active,
-                                            ws, lds, s)
+                                            ws, lds, only_front, s)
                       : segp_prec<MODE_BWD>(B, prec, in_prec, out_prec, probs, chains, nchains, io, io_val, waves, active,
-                                            ws, lds, s);
+                                            ws, lds, only_front, s);
 }
 
 int64_t seg_ws_elems(int nchains, int waves) { return (int64_t)nchains * SEG * 64 * waves; }

@@ -30,7 +30,7 @@ EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_reassemble"
            "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "sweep_refactor_batch", "helm_batch_tune",
            "helm_batch_set_graph", "helm_free", "sweep_free",
            "helm_batch_free", "helm_timing_enable", "helm_timing_read"]
-PHASES = ["assemble", "factor", "sweep_fwd", "sweep_mid", "sweep_bwd", "matvec", "krylov"]
+PHASES = ["assemble", "factor", "sweep_fwd", "sweep_mid", "sweep_bwd", "matvec", "krylov", "sweep_front"]
 
 
 class HelmError(RuntimeError):
@@ -41,7 +41,8 @@ class HelmError(RuntimeError):
 
 class HelmParams(C.Structure):
     _fields_ = [("n", C.c_int32), ("omega", C.c_double), ("alpha", C.c_double), ("pml_w", C.c_int32),
-                ("mpml_w", C.c_int32), ("pml_C", C.c_double), ("b_convention", C.c_int32)]
+                ("mpml_w", C.c_int32), ("pml_C", C.c_double), ("b_convention", C.c_int32),
+                ("layers_d", C.c_int32), ("exact_mode", C.c_int32)]
 
 
 def _load() -> C.CDLL:
@@ -139,9 +140,12 @@ class Params:
     mpml_w: int = 12
     C: float = 20.0
     b_convention: int = 0
+    layers_d: int = 1
+    exact_mode: int = 0
 
     def c_struct(self) -> HelmParams:
-        return HelmParams(self.n, self.omega, self.alpha, self.pml_w, self.mpml_w, self.C, self.b_convention)
+        return HelmParams(self.n, self.omega, self.alpha, self.pml_w, self.mpml_w, self.C, self.b_convention,
+                          self.layers_d, self.exact_mode)
 
     @property
     def B(self) -> int:
@@ -269,10 +273,10 @@ def timing_enable(on: bool = True):
 
 def timing_read(reset: bool = True):
     """{phase: (milliseconds, launches)} summed since the last reset."""
-    ms = (C.c_double * 7)()
-    ln = (C.c_int64 * 7)()
+    ms = (C.c_double * len(PHASES))()
+    ln = (C.c_int64 * len(PHASES))()
     _check(_lib.helm_timing_read(ms, ln, 1 if reset else 0))
-    return {PHASES[i]: (ms[i], int(ln[i])) for i in range(7)}
+    return {PHASES[i]: (ms[i], int(ln[i])) for i in range(len(PHASES))}
 
 
 @dataclass
@@ -346,13 +350,15 @@ class Batch:
     def tune(self, reps: int = 2, stream=None) -> dict:
         """Pick the fastest sweep schedule for this batch by timing every candidate (a7 autotuner).
 
-        Overwrites the batch's Krylov work space.  Returns {"segmented", "ksplit", "waves", "ms_per_apply"}:
-        for the segmented chains waves is their workgroup size and ksplit 0; for the plain chains the
-        split and the waves per chain."""
+        Overwrites the batch's Krylov work space.  Returns {"kind", "segmented", "ksplit", "waves",
+        "ms_per_apply"}: kind 0 plain chains (ksplit = the split, waves per chain), 1 segmented chains
+        (waves = their workgroup size, ksplit 0), 2 compressed moving chains (ksplit = right-hand sides per
+        workgroup, waves = its waves); segmented = 1 for kinds 1 and 2."""
         ks, wv, sg, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
         _check(_lib.helm_batch_tune(self._h, int(reps), C.c_void_p(_stream(stream)), C.byref(ks), C.byref(wv),
                                     C.byref(sg), C.byref(ms)))
-        return {"segmented": sg.value, "ksplit": ks.value, "waves": wv.value, "ms_per_apply": ms.value}
+        return {"kind": sg.value, "segmented": 1 if sg.value else 0, "ksplit": ks.value, "waves": wv.value,
+                "ms_per_apply": ms.value}
 
     def refactor(self, stream=None):
         """Recompute the factors of every member in place (a2 over the whole batch, two launches)."""

@@ -39,14 +39,15 @@ def test_library_exports_every_declared_symbol(hs):
 
 
 def _params(hs, **kw):
-    d = dict(n=63, omega=50.0, alpha=2.0, pml_w=8, mpml_w=8, pml_C=20.0, b_convention=0)
+    d = dict(n=63, omega=50.0, alpha=2.0, pml_w=8, mpml_w=8, pml_C=20.0, b_convention=0, layers_d=1, exact_mode=0)
     d.update(kw)
     return hs.HelmParams(**d)
 
 
 @pytest.mark.parametrize("bad", [dict(n=20), dict(omega=0.0), dict(omega=float("nan")), dict(alpha=-1.0),
                                  dict(pml_w=0), dict(mpml_w=0), dict(mpml_w=5), dict(pml_C=0.0),
-                                 dict(b_convention=2), dict(pml_w=40), dict(n=40000)])
+                                 dict(b_convention=2), dict(pml_w=40), dict(n=40000), dict(layers_d=12),
+                                 dict(layers_d=-1), dict(exact_mode=1)])
 def test_assemble_rejects_bad_params(hs, bad):
     """Parameter checks run before any device call and return HELM_EINVAL with a message."""
     p = _params(hs, **bad)

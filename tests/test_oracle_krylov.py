@@ -75,3 +75,40 @@ def test_golden_paper_table_band():
     M = S.factor(par, pr.c)
     r = K.gmres_left(lambda v: A @ v, lambda v: S.apply_sweep(M, v), pr.f[0], tol=1e-3)
     assert r.converged and r.iters <= max(iters)
+
+
+def test_gmres_left_identity_preconditioner_matches_direct():
+    """Left-preconditioned GMRES with M = I and no stop before N steps is plain GMRES: it returns
+    A^{-1} f (dense solve) and its last estimate is the true relative residual."""
+    rng = np.random.default_rng(1)
+    N = 36
+    A = sp.csr_matrix(np.eye(N) * 3 + rng.standard_normal((N, N)) * 0.4 + 1j * rng.standard_normal((N, N)) * 0.4)
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    r = K.gmres_left(lambda v: A @ v, lambda v: v, f, tol=1e-13, maxit=N + 4)
+    xd = np.linalg.solve(A.toarray(), f)
+    np.testing.assert_allclose(r.x, xd, rtol=1e-10)
+    assert r.converged and r.relres <= 1e-12
+
+
+def test_gmres_left_estimate_is_preconditioned_residual():
+    """The left form's stopping estimate is the preconditioned residual ||M(f - A u)|| / ||M f||
+    (Section 2.3's system M A u = M f), not the plain one: at every stop it equals the explicit value
+    computed from the returned u, for a non-trivial M (a diagonal with a wide spread, where the two
+    residuals differ: a diagonal whose entries spread over a factor 30)."""
+    rng = np.random.default_rng(4)
+    N = 60
+    A = sp.csr_matrix(np.diag(np.linspace(1, 30, N)) + 0.05 * rng.standard_normal((N, N))
+                      + 0.05j * rng.standard_normal((N, N)))
+    d = (1.0 + 0.3 * np.exp(1j * np.linspace(0, 2, N))) / np.linspace(1, 30, N)   # M A near I, weights spread 30x
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    M = lambda v: d * v
+    for tol in (1e-2, 1e-5, 1e-9):
+        r = K.gmres_left(lambda v: A @ v, M, f, tol=tol, maxit=N)
+        assert r.iters < N // 2
+        pre = np.linalg.norm(M(f - A @ r.x)) / np.linalg.norm(M(f))
+        plain = np.linalg.norm(f - A @ r.x) / np.linalg.norm(f)
+        assert abs(r.history[-1] - pre) <= 1e-8 * pre + 1e-15
+        assert r.converged and pre <= tol
+        assert abs(r.relres - plain) <= 1e-12 * plain + 1e-15
+        # monotone (unrestarted GMRES minimises the preconditioned residual over a growing space)
+        assert np.all(np.diff(r.history) <= 1e-14)

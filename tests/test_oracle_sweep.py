@@ -188,3 +188,50 @@ def test_middle_strip_damped_alike_on_both_sides(mw):
         Hu = S.sub_operator(par, c, up).toarray()
         Pb = np.arange(par.B * n).reshape(par.B, n)[::-1, :].ravel()
         np.testing.assert_allclose(Hu, Hl[np.ix_(Pb, Pb)], rtol=1e-13, atol=1e-13 * np.abs(Hl).max())
+
+
+@pytest.mark.parametrize("n,w", [(29, 4), (30, 3), (41, 6)])
+def test_moving_strips_equal_front_blocks_for_x2_independent_c(n, w):
+    """Section 2.2, s2^m(x2) = s(sigma_2(x2 - (m - b)h)): the moving PML of layer m is the physical
+    bottom PML shifted up to the strip.  With equal physical and moving widths and a velocity that
+    does not depend on x2, every lower strip operator H_m is therefore entry for entry the front block
+    A_alpha[F, F], and every upper one A_alpha[E, E].  An offset of one row in either front's
+    profile (a consistent off-by-one keeps the monotone-trend and mirror pins) breaks this."""
+    par = H.Params(n=n, omega=2 * math.pi * 3.5, alpha=2.0, pml_w=w, mpml_w=w)
+    # c depends on x1 only: the same row repeated
+    c = np.tile(workloads.velocity_waveguide(n, seed=3).reshape(n, n)[n // 2], (n, 1)).ravel()
+    A = H.assemble(par, c, shifted=True).toarray()
+    B = par.B
+    AF = A[:B * n, :B * n]
+    AE = A[(n - B) * n:, (n - B) * n:]
+    specs = S.subproblem_specs(par)
+    assert len(specs['lower']) > 2 and len(specs['upper']) > 2
+    for spec in specs['lower']:
+        Hm = S.sub_operator(par, c, spec).toarray()
+        np.testing.assert_allclose(Hm, AF, rtol=1e-13, atol=1e-13 * np.abs(AF).max())
+    for spec in specs['upper']:
+        Hm = S.sub_operator(par, c, spec).toarray()
+        np.testing.assert_allclose(Hm, AE, rtol=1e-13, atol=1e-13 * np.abs(AE).max())
+
+
+def test_b_convention_literal_is_a_relabelling():
+    """The paper-literal width convention (eta = w h, B = w) with width w + 1 builds the same PMLs and
+    strips as the default (eta = (w + 1) h, B = w + 1) with width w: equal B, eta and M_alpha."""
+    n, w = 33, 4
+    p0 = H.Params(n=n, omega=2 * math.pi * 3, alpha=2.0, pml_w=w, mpml_w=w, b_convention=0)
+    p1 = H.Params(n=n, omega=2 * math.pi * 3, alpha=2.0, pml_w=w + 1, mpml_w=w + 1, b_convention=1)
+    assert p0.B == p1.B == w + 1
+    assert p0.eta_phys == p1.eta_phys and p0.eta_move == p1.eta_move
+    c = workloads.velocity_grf(n, seed=8)
+    f = workloads.random_rhs(n, 2, seed=9)
+    u0 = S.apply_sweep(S.factor(p0, c), f)
+    u1 = S.apply_sweep(S.factor(p1, c), f)
+    np.testing.assert_array_equal(u0, u1)
+    # and the literal convention is itself exact in exact mode (its B = w strips, eta = w h)
+    p2 = H.Params(n=n, omega=2 * math.pi * 3, alpha=2.0, pml_w=w, mpml_w=w, b_convention=1)
+    assert p2.B == w and abs(p2.eta_move - w * p2.h) < 1e-15
+    Aa = H.assemble(p2, c, shifted=True).tocsc()
+    u2 = S.apply_sweep(S.factor(p2, c, exact=True), f)
+    for k in range(2):
+        ud = spla.spsolve(Aa, f[k])
+        assert np.linalg.norm(u2[k] - ud) <= 1e-11 * np.linalg.norm(ud)
