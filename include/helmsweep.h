@@ -128,6 +128,21 @@ int64_t sweep_factor_bytes(sweep_factors_t M);
  *   both.  f and u must not overlap.  Asynchronous. */
 int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nrhs, int32_t vec_prec, void* stream);
 
+/* Allocation-free form of sweep_apply, for callers that cannot allocate device memory: code running
+ * under HIP graph capture, allocation-free serving loops, harnesses that forbid hipMalloc.  The same
+ * operation, kernels, schedule and results as sweep_apply (u = M_alpha f, same arguments); the chain
+ * tables and sweep workspaces, which sweep_apply keeps in memory the handle allocates, go instead to
+ * one statically allocated scratch array of HELM_NOALLOC_SCRATCH_BYTES per GPU (created when the
+ * library is loaded on that GPU, held until the process ends).  No hipMalloc / hipFree or allocating
+ * library call is made; the tables are copied into the scratch with hipMemcpyAsync on `stream` (a call
+ * whose nrhs differs from the previous one on the same factors first synchronises `stream`).
+ * Returns HELM_ENOMEM (and launches nothing) when the call needs more scratch than that, e.g. n = 511
+ * with 64 right-hand sides in complex128.  Every call on one GPU shares its scratch, which keeps
+ * the last call's contents (no kernel reads scratch it has not written in the same call): calls that
+ * overlap on one GPU (other streams, other threads) race, so serialise them. */
+#define HELM_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+int sweep_apply_noalloc(sweep_factors_t M, const void* f, void* u, int32_t nrhs, int32_t vec_prec, void* stream);
+
 /* One subproblem's T~ (test hook for parity of a2): solve H_s x = g for subproblem `sub`
  * (0 = F, 1..L = lower layers B+1.., L+1 = E, L+2.. = upper layers n-B.., last = middle) with
  * g and x device complex128 [nrhs][rows][n] in the strip's local row order (local row 0 is the row

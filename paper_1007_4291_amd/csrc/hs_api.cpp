@@ -173,6 +173,8 @@ struct sweep_factors_s {
     int chains_nrhs = -1, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1, waves = 1, ncch = 0, cwaves = 0, crq = 8;
     int nsegch = 0, seg_wg = 0, kind = 0;   // kind 1: segmented chains, 2: compressed moving chains
     helm_batch_t solo = nullptr;    // cached batch of one for fgmres_solve
+    std::unique_ptr<SoloPlan> na_plan;   // host tables of the last sweep_apply_noalloc call
+    int na_nrhs = -1;
     int solo_nrhs = -1, solo_restart = -1;
     ~sweep_factors_s();
 };
@@ -796,6 +798,42 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
     const SoloDev D{M->chains.as<ChainDev>(), M->mids.as<ChainDev>(), M->segch.as<ChainDev>(), M->cchains.as<ChainDev>(),
                     M->nchains, M->nmids, M->nsegch, M->ncch, M->ks_chain, M->ks_mid, M->waves, M->seg_wg, M->kind,
                     M->cwaves, M->crq, M->spill.p, M->segws.p};
+    return solo_launch(M, D, f, u, vec_prec, s);
+}
+
+extern "C" int sweep_apply_noalloc(sweep_factors_t M, const void* f, void* u, int32_t nrhs, int32_t vec_prec,
+                                   void* stream) {
+    int rc = check_apply_args(M, f, u, nrhs, vec_prec);
+    if (rc || nrhs == 0) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // The plan is host data kept in the handle, so that the asynchronous copies below read memory that
+    // outlives the call.  It changes only with nrhs; the stream's earlier copies from the old plan are
+    // waited for before it is replaced.
+    if (!M->na_plan || M->na_nrhs != nrhs) {
+        if (M->na_plan) HIPCHK(hipStreamSynchronize(s));
+        M->na_plan.reset(new SoloPlan(solo_plan(M, nrhs)));
+        M->na_nrhs = nrhs;
+    }
+    const SoloPlan& P = *M->na_plan;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_ch = 0, o_md = o_ch + up(sizeof(ChainDev) * P.ch.size()), o_sc = o_md + up(sizeof(ChainDev) * P.md.size()),
+                 o_cc = o_sc + up(sizeof(ChainDev) * P.sc.size()), o_sp = o_cc + up(sizeof(ChainDev) * P.cc.size()),
+                 o_ws = o_sp + up(P.spill_bytes), total = o_ws + up(P.segws_bytes);
+    if (total > (size_t)HELM_NOALLOC_SCRATCH_BYTES)
+        return fail(HELM_ENOMEM, "sweep_apply_noalloc: n=%d with %d right-hand sides needs %zu bytes of scratch, the "
+                                 "static scratch holds %d", M->A->n, nrhs, total, (int)HELM_NOALLOC_SCRATCH_BYTES);
+    char* base = (char*)noalloc_scratch();
+    if (!base) return fail(HELM_EHIP, "sweep_apply_noalloc: %s", noalloc_error());
+    HIPCHK(hipMemcpyAsync(base + o_ch, P.ch.data(), sizeof(ChainDev) * P.ch.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(base + o_md, P.md.data(), sizeof(ChainDev) * P.md.size(), hipMemcpyHostToDevice, s));
+    if (!P.sc.empty())
+        HIPCHK(hipMemcpyAsync(base + o_sc, P.sc.data(), sizeof(ChainDev) * P.sc.size(), hipMemcpyHostToDevice, s));
+    if (!P.cc.empty())
+        HIPCHK(hipMemcpyAsync(base + o_cc, P.cc.data(), sizeof(ChainDev) * P.cc.size(), hipMemcpyHostToDevice, s));
+    const SoloDev D{(const ChainDev*)(base + o_ch), (const ChainDev*)(base + o_md), (const ChainDev*)(base + o_sc),
+                    (const ChainDev*)(base + o_cc), (int)P.ch.size(), (int)P.md.size(), (int)P.sc.size(),
+                    (int)P.cc.size(), P.ks_chain, P.ks_mid, P.waves, P.seg_wg, P.kind, P.cwaves, P.crq, base + o_sp,
+                    base + o_ws};
     return solo_launch(M, D, f, u, vec_prec, s);
 }
 

@@ -190,4 +190,9 @@ bool launch_chains_comp(int B, int seg, int rq, int in_prec, int out_prec, int p
                         const int32_t* active, hipStream_t s);
 size_t chainc_lds_bytes(int B, int seg, int rq, int waves);
 
+// Device address of the allocation-free entry point's static scratch array on the current device
+// (looked up once per device), or nullptr with noalloc_error() set.
+void* noalloc_scratch();
+const char* noalloc_error();
+
 }  // namespace hs

@@ -26,7 +26,7 @@ HELM_C64 = 1
 
 # every symbol the header declares
 EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_reassemble", "helm_problem_n", "helm_matvec",
-           "sweep_factor", "sweep_refactor", "sweep_factor_bytes", "sweep_apply", "sweep_subsolve", "sweep_num_subproblems", "sweep_subproblem_rows",
+           "sweep_factor", "sweep_refactor", "sweep_factor_bytes", "sweep_apply", "sweep_apply_noalloc", "sweep_subsolve", "sweep_num_subproblems", "sweep_subproblem_rows",
            "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "sweep_refactor_batch", "helm_batch_tune",
            "helm_batch_set_graph", "helm_free", "sweep_free",
            "helm_batch_free", "helm_timing_enable", "helm_timing_read"]
@@ -61,6 +61,7 @@ def _load() -> C.CDLL:
         "sweep_refactor": (C.c_int, [vp, vp]),
         "sweep_factor_bytes": (C.c_int64, [vp]),
         "sweep_apply": (C.c_int, [vp, vp, vp, i32, i32, vp]),
+        "sweep_apply_noalloc": (C.c_int, [vp, vp, vp, i32, i32, vp]),
         "sweep_subsolve": (C.c_int, [vp, i32, vp, vp, i32, vp]),
         "sweep_num_subproblems": (C.c_int, [vp]),
         "sweep_subproblem_rows": (C.c_int, [vp, i32]),
@@ -242,6 +243,17 @@ class Factors:
             raise ValueError("u must match f in dtype and size")
         _check(_lib.sweep_apply(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), f.numel() // self.A.N,
                                 _prec_of(f), C.c_void_p(_stream(stream))))
+        return u
+
+    def apply_noalloc(self, f, u, stream=None):
+        """u = M_alpha f through the allocation-free entry point (library scratch, no device allocation);
+        u must be given."""
+        _check_vec(f, self.A.N, "f")
+        _check_vec(u, self.A.N, "u")
+        if u.dtype != f.dtype or u.numel() != f.numel():
+            raise ValueError("u must match f in dtype and size")
+        _check(_lib.sweep_apply_noalloc(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()),
+                                        f.numel() // self.A.N, _prec_of(f), C.c_void_p(_stream(stream))))
         return u
 
     def subsolve(self, sub: int, g, x=None, stream=None):
