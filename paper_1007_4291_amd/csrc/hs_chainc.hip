@@ -198,10 +198,12 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
 // physical segment of the strips
 // ---------------------------------------------------------------------------------------------
 template <int BS, int SEG, int RQ> struct ChainCShape {
-    // LDS (complex64): gamma / layer row by segment and column, then per segment qf, qb, c_in, x_above
+    // LDS (complex64), per segment: gamma / layer row by column, qf, qb, c_in, x_above, and the strip's
+    // Phi and Phi^T of the segment (staged for the spines)
     static constexpr int GAM = SEG * RQ;
     static constexpr int VEC = BS * RQ;
-    static constexpr int PER_SEG = GAM + 4 * VEC;
+    static constexpr int PHI = BS * BS;
+    static constexpr int PER_SEG = GAM + 4 * VEC + 2 * PHI;
 };
 
 template <int BS, int SEG, int MODE, class TI, class TO, int RQ>
@@ -219,6 +221,7 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     float2* const qb = qf + nwv * LS::VEC;
     float2* const cin = qb + nwv * LS::VEC;
     float2* const xab = cin + nwv * LS::VEC;
+    float2* const phl = xab + nwv * LS::VEC;            // [nwv][2][BS][BS]: Phi, Phi^T of each segment
 
     const ChainDev ch = chains[blockIdx.x];
     if (ch.nq == 0) return;
@@ -245,157 +248,231 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     constexpr int NQH = 64 / SEG;                      // right-hand-side lanes per column in the input step
     float2* const gs = gam + s * LS::GAM;
 
+    // A spine (one wave): v <- Mat_ss v + add_ss over the segments ss in LU order (up) or reverse LU
+    // order, storing the value entering each segment in store[ss]; Mat = Phi (mat 0) or Phi^T (mat 1).
+    // Lane (r, q): row r < BS of right-hand side q (and q + 4 for 8 per workgroup); the rows of 16 lanes
+    // are the right-hand sides, so the other rows' values come by DPP row broadcast, and the matrix
+    // row of the next step is read from LDS while this step's products run.
+    auto spine = [&](int mat, bool up, const float2* addv, float2* store) __attribute__((always_inline)) {
+        constexpr int H = RQ / 4;
+        const int sr = lane & 15, sq = lane >> 4, srr = sr < BS ? sr : BS - 1;
+        float2 v[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) v[h] = make_float2(0.f, 0.f);
+        auto seg_at = [&](int k) { return up ? k : S - 1 - k; };
+        float2 pr[BS];
+        {
+            const float2* const pb = phl + seg_at(0) * 2 * LS::PHI + mat * LS::PHI + srr * BS;
+#pragma unroll
+            for (int kk = 0; kk < BS; ++kk) pr[kk] = pb[kk];
+        }
+        for (int k = 0; k < S; ++k) {
+            const int ss = seg_at(k);
+            float2 ad[H];
+#pragma unroll
+            for (int h = 0; h < H; ++h) ad[h] = addv[(ss * BS + srr) * RQ + sq + 4 * h];
+            if (sr < BS) {
+#pragma unroll
+                for (int h = 0; h < H; ++h) store[(ss * BS + sr) * RQ + sq + 4 * h] = v[h];
+            }
+            float2 nv[H];
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                float a0x, a0y, a1x, a1y;
+                static_for<BS>([&](auto KC) __attribute__((always_inline)) {
+                    constexpr int kk = decltype(KC)::value;
+                    if constexpr (kk == 0) cmul_rowbcast<kk>(a0x, a0y, pr[kk].x, pr[kk].y, v[h].x, v[h].y);
+                    else if constexpr (kk == 1) cmul_rowbcast<kk>(a1x, a1y, pr[kk].x, pr[kk].y, v[h].x, v[h].y);
+                    else if constexpr (kk & 1) cfma_rowbcast<kk>(a1x, a1y, pr[kk].x, pr[kk].y, v[h].x, v[h].y);
+                    else cfma_rowbcast<kk>(a0x, a0y, pr[kk].x, pr[kk].y, v[h].x, v[h].y);
+                });
+                if constexpr (BS == 1) { a1x = 0.f; a1y = 0.f; }
+                nv[h] = sr < BS ? make_float2(ad[h].x + (a0x + a1x), ad[h].y + (a0y + a1y)) : make_float2(0.f, 0.f);
+            }
+            if (k + 1 < S) {
+                const float2* const pb = phl + seg_at(k + 1) * 2 * LS::PHI + mat * LS::PHI + srr * BS;
+#pragma unroll
+                for (int kk = 0; kk < BS; ++kk) pr[kk] = pb[kk];
+            }
+#pragma unroll
+            for (int h = 0; h < H; ++h) v[h] = nv[h];
+        }
+    };
+
+    // Global data of a strip is requested in few round trips: its gamma columns G1, input row and
+    // layer-row couplings together at the start of the strip, the backward phase's output row during the
+    // backward spine, G2 and G3 all at once where they are used.
+    auto strip_of = [&](int i) { return MODE == MODE_FWD ? i + 1 : L - i; };     // strip index in its front
+    auto strip_blk = [&](int i) -> const HS_GLOBAL float2* {
+        return cmp + ((int64_t)(sbase + strip_of(i) - 1) * S + s) * SH::SIZE;
+    };
+    constexpr int NH0 = RQ / NQH;                      // input values per lane
+    const int icc = lane % SEG, iqh = lane / SEG;      // input step: this lane's column and right-hand sides
+    float2 g1[SEG];
+    double2 fin_v[NH0];                                 // forward phase: f on the next strip's layer row
+    float2 cpl_v;                                       // the next strip's coupling at this lane's column
+    auto prefetch_strip = [&](int i) __attribute__((always_inline)) {
+        const HS_GLOBAL float2* const b = strip_blk(i);
+        const HS_GLOBAL float2* const b1 = b + SH::O_G1 + (lane < SH::R1P ? lane : 0);
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) g1[j] = gld(b1 + j * SH::R1P);
+        const int st = strip_of(i), cd = (st & 1) ? -1 : 1;
+        const int j = cd > 0 ? icc : SEG - 1 - icc;
+        cpl_v = gld(b + SH::O_CPL + 2 * j + (MODE == MODE_FWD ? 0 : 1));
+        if constexpr (MODE == MODE_FWD) {
+            const int jl = jF + dirF * st, col = s * SEG + icc;
+#pragma unroll
+            for (int h = 0; h < NH0; ++h) {
+                const int q = iqh + NQH * h;
+                fin_v[h] = (col < n && q < ch.nq)
+                               ? ld2(fin + (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col)
+                               : make_double2(0.0, 0.0);
+            }
+        }
+    };
     for (int i = 0; i < L; ++i) {
-        const int st = MODE == MODE_FWD ? i + 1 : L - i;      // strip index in its front (1..L)
+        prefetch_strip(i);      // G1, the input row and couplings together: one memory latency per strip
+        const int st = strip_of(i);                            // strip index in its front (1..L)
         const int jl = jF + dirF * st;                         // layer row
         const int cd = (st & 1) ? -1 : 1;                      // column direction of its block LU
-        const HS_GLOBAL float2* const blk = cmp + ((int64_t)(sbase + st - 1) * S + s) * SH::SIZE;
+        const HS_GLOBAL float2* const blk = strip_blk(i);
         // ---- 0. the strip's layer-row input on this segment's columns
         {
-            const int cc = lane % SEG, qh = lane / SEG;
-            const int col = s * SEG + cc;
-            const int j = cd > 0 ? cc : SEG - 1 - cc;
-            const float2 a = gld(blk + SH::O_CPL + 2 * j + (MODE == MODE_FWD ? 0 : 1));
+            const int col = s * SEG + icc;
 #pragma unroll
-            for (int h = 0; h < RQ / NQH; ++h) {
-                const int q = qh + NQH * h;
+            for (int h = 0; h < NH0; ++h) {
+                const int q = iqh + NQH * h;
                 float2 g = make_float2(0.f, 0.f);
                 if (col < n && q < ch.nq) {
                     const int64_t rb = (int64_t)(ch.rhs0 + q) * N;
                     if (MODE == MODE_FWD) {
-                        const double2 f = ld2(fin + rb + (int64_t)(jl - 1) * n + col);
                         const float2 yp = i == 0 ? ccast<float, double>(ld2(uout + rb + (int64_t)(jl - dirF - 1) * n + col))
-                                                 : gs[cc * RQ + q];
-                        g = csub<float>(make_float2((float)f.x, (float)f.y), cmul<float>(a, yp));
+                                                 : gs[icc * RQ + q];
+                        g = csub<float>(make_float2((float)fin_v[h].x, (float)fin_v[h].y), cmul<float>(cpl_v, yp));
                     } else {
                         const float2 yn = i == 0 ? ccast<float, double>(ld2(uout + rb + (int64_t)(cmid - 1) * n + col))
-                                                 : gs[cc * RQ + q];
-                        g = cmul<float>(a, yn);
+                                                 : gs[icc * RQ + q];
+                        g = cmul<float>(cpl_v, yn);
                     }
                 }
-                gs[cc * RQ + q] = g;
+                gs[icc * RQ + q] = g;
             }
         }
         wave_sync();
-        // ---- 1. qf, qb and the local part of y from gamma
-        float2 yl[RQ];
+        // ---- 1. qf, qb and the local part of y from gamma; meanwhile this segment's Phi and Phi^T go to
+        // LDS for the spines
+        constexpr int NPH = (2 * BS * BS + 63) / 64;
         {
             float2 acc[RQ];
 #pragma unroll
             for (int q = 0; q < RQ; ++q) acc[q] = make_float2(0.f, 0.f);
-#pragma unroll 4
-            for (int j = 0; j < SEG; ++j) {
-                const float2 gcoef = gld(blk + SH::O_G1 + j * SH::R1P + (lane < SH::R1P ? lane : 0));
-                const int cc = cd > 0 ? j : SEG - 1 - j;
+            // in groups of 2 columns, so that only one group's gamma values are in flight from LDS
+            static_for<SEG / 2>([&](auto GC) __attribute__((always_inline)) {
+                static_for<2>([&](auto UC) __attribute__((always_inline)) {
+                    constexpr int j = 2 * decltype(GC)::value + decltype(UC)::value;
+                    const int cc = cd > 0 ? j : SEG - 1 - j;
 #pragma unroll
-                for (int q = 0; q < RQ; ++q) acc[q] = cfma<float>(gcoef, gs[cc * RQ + q], acc[q]);
-            }
+                    for (int q = 0; q < RQ; ++q) acc[q] = cfma<float>(g1[j], gs[cc * RQ + q], acc[q]);
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            });
+            wave_sync();          // every lane has read gamma: the layer-row values y take its place
             if (lane < BS) {
 #pragma unroll
                 for (int q = 0; q < RQ; ++q) qf[(s * BS + lane) * RQ + q] = acc[q];
             } else if (lane < 2 * BS) {
 #pragma unroll
                 for (int q = 0; q < RQ; ++q) qb[(s * BS + lane - BS) * RQ + q] = acc[q];
+            } else if (lane < SH::R1) {
+                const int jj = lane - 2 * BS, cc = cd > 0 ? jj : SEG - 1 - jj;
+#pragma unroll
+                for (int q = 0; q < RQ; ++q) gs[cc * RQ + q] = acc[q];
+            }
+        }
+        {
+            float2 phr[NPH];
+#pragma unroll
+            for (int u = 0; u < NPH; ++u) {
+                const int e = lane + 64 * u;
+                phr[u] = gld(blk + SH::O_PHI + (e < 2 * BS * BS ? e : 0));   // Phi then Phi^T, contiguous
             }
 #pragma unroll
-            for (int q = 0; q < RQ; ++q) yl[q] = acc[q];
+            for (int u = 0; u < NPH; ++u) {
+                const int e = lane + 64 * u;
+                if (e < 2 * BS * BS) phl[s * 2 * LS::PHI + e] = phr[u];
+            }
         }
         __syncthreads();
         // ---- 2. forward spine (wave 0): carries entering every segment, in the strip's LU order
-        const int sr = lane & 15, sq = lane >> 4, srr = sr < BS ? sr : BS - 1;
-        if (wv == 0) {
-            float2 c[RQ / 4];
-#pragma unroll
-            for (int h = 0; h < RQ / 4; ++h) c[h] = make_float2(0.f, 0.f);
-            for (int k = 0; k < S; ++k) {
-                const int ss = cd > 0 ? k : S - 1 - k;
-                const HS_GLOBAL float2* const pb = cmp + ((int64_t)(sbase + st - 1) * S + ss) * SH::SIZE + SH::O_PHI + srr * BS;
-                if (sr < BS) {
-#pragma unroll
-                    for (int h = 0; h < RQ / 4; ++h) cin[(ss * BS + sr) * RQ + sq + 4 * h] = c[h];
-                }
-                wave_sync();
-#pragma unroll
-                for (int h = 0; h < RQ / 4; ++h) c[h] = qf[(ss * BS + srr) * RQ + sq + 4 * h];
-#pragma unroll 4
-                for (int kk = 0; kk < BS; ++kk) {
-                    const float2 p = gld(pb + kk);
-#pragma unroll
-                    for (int h = 0; h < RQ / 4; ++h) c[h] = cfma<float>(p, cin[(ss * BS + kk) * RQ + sq + 4 * h], c[h]);
-                }
-                wave_sync();
-            }
-        }
+        if (wv == 0) spine(0, cd > 0, qf, cin);
         __syncthreads();
         // ---- 3. qb += W c_in, y += VS c_in
         if (lane >= BS && lane < SH::R1) {
-            const int ii = lane - BS;
+            // G2 entries of this lane (rows B .. R1 of the c_in block), all requested at once
+            float2 g2[BS];
+#pragma unroll
+            for (int k = 0; k < BS; ++k) g2[k] = gld(blk + SH::O_G2 + k * SH::R2P + lane - BS);
             float2 acc[RQ];
 #pragma unroll
             for (int q = 0; q < RQ; ++q) acc[q] = make_float2(0.f, 0.f);
-#pragma unroll 4
-            for (int k = 0; k < BS; ++k) {
-                const float2 w = gld(blk + SH::O_G2 + k * SH::R2P + ii);
+            static_for<(BS + 3) / 4>([&](auto GC) __attribute__((always_inline)) {
+                static_for<4>([&](auto UC) __attribute__((always_inline)) {
+                    constexpr int k = 4 * decltype(GC)::value + decltype(UC)::value;
+                    if constexpr (k < BS) {
 #pragma unroll
-                for (int q = 0; q < RQ; ++q) acc[q] = cfma<float>(w, cin[(s * BS + k) * RQ + q], acc[q]);
-            }
-            if (lane < 2 * BS) {
+                        for (int q = 0; q < RQ; ++q) acc[q] = cfma<float>(g2[k], cin[(s * BS + k) * RQ + q], acc[q]);
+                    }
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            });
+            float2* const d = lane < 2 * BS ? &qb[(s * BS + lane - BS) * RQ]
+                                            : &gs[(cd > 0 ? lane - 2 * BS : SEG - 1 - (lane - 2 * BS)) * RQ];
 #pragma unroll
-                for (int q = 0; q < RQ; ++q) {
-                    float2* const d = &qb[(s * BS + lane - BS) * RQ + q];
-                    *d = cadd<float>(*d, acc[q]);
-                }
-            } else {
+            for (int q = 0; q < RQ; ++q) d[q] = cadd<float>(d[q], acc[q]);
+        }
+        // G3 entries of this lane (the x_above block) and, in the backward phase, the current values of the
+        // output row, requested before the backward spine
+        const int jj5 = lane >= 2 * BS && lane < SH::R1 ? lane - 2 * BS : 0;
+        const int cc5 = cd > 0 ? jj5 : SEG - 1 - jj5;
+        const int col5 = s * SEG + cc5;
+        const bool out5 = lane >= 2 * BS && lane < SH::R1 && col5 < n;
+        float2 uold[MODE == MODE_BWD ? RQ : 1];
+        if constexpr (MODE == MODE_BWD) {
 #pragma unroll
-                for (int q = 0; q < RQ; ++q) yl[q] = cadd<float>(yl[q], acc[q]);
-            }
+            for (int q = 0; q < RQ; ++q)
+                uold[q] = (out5 && q < ch.nq)
+                              ? ccast<float, double>(ld2(uout + (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col5))
+                              : make_float2(0.f, 0.f);
         }
         __syncthreads();
         // ---- 4. backward spine (wave 0): values entering every segment from above, reverse LU order
-        if (wv == 0) {
-            float2 x[RQ / 4];
-#pragma unroll
-            for (int h = 0; h < RQ / 4; ++h) x[h] = make_float2(0.f, 0.f);
-            for (int k = 0; k < S; ++k) {
-                const int ss = cd > 0 ? S - 1 - k : k;
-                const HS_GLOBAL float2* const pb = cmp + ((int64_t)(sbase + st - 1) * S + ss) * SH::SIZE + SH::O_PHIT + srr * BS;
-                if (sr < BS) {
-#pragma unroll
-                    for (int h = 0; h < RQ / 4; ++h) xab[(ss * BS + sr) * RQ + sq + 4 * h] = x[h];
-                }
-                wave_sync();
-#pragma unroll
-                for (int h = 0; h < RQ / 4; ++h) x[h] = qb[(ss * BS + srr) * RQ + sq + 4 * h];
-#pragma unroll 4
-                for (int kk = 0; kk < BS; ++kk) {
-                    const float2 p = gld(pb + kk);
-#pragma unroll
-                    for (int h = 0; h < RQ / 4; ++h) x[h] = cfma<float>(p, xab[(ss * BS + kk) * RQ + sq + 4 * h], x[h]);
-                }
-                wave_sync();
-            }
-        }
+        if (wv == 0) spine(1, cd < 0, qb, xab);
         __syncthreads();
         // ---- 5. y += US x_above; the strip's layer-row output
         if (lane >= 2 * BS && lane < SH::R1) {
-            const int jj = lane - 2 * BS;
-#pragma unroll 4
-            for (int k = 0; k < BS; ++k) {
-                const float2 us = gld(blk + SH::O_G3 + k * SH::R3P + jj);
+            float2 g3[BS];
 #pragma unroll
-                for (int q = 0; q < RQ; ++q) yl[q] = cfma<float>(us, xab[(s * BS + k) * RQ + q], yl[q]);
-            }
-            const int cc = cd > 0 ? jj : SEG - 1 - jj;
-            const int col = s * SEG + cc;
+            for (int k = 0; k < BS; ++k) g3[k] = gld(blk + SH::O_G3 + k * SH::R3P + jj5);
+            float2 yl[RQ];
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) yl[q] = gs[cc5 * RQ + q];
+            static_for<(BS + 3) / 4>([&](auto GC) __attribute__((always_inline)) {
+                static_for<4>([&](auto UC) __attribute__((always_inline)) {
+                    constexpr int k = 4 * decltype(GC)::value + decltype(UC)::value;
+                    if constexpr (k < BS) {
+#pragma unroll
+                        for (int q = 0; q < RQ; ++q) yl[q] = cfma<float>(g3[k], xab[(s * BS + k) * RQ + q], yl[q]);
+                    }
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            });
 #pragma unroll
             for (int q = 0; q < RQ; ++q) {
                 float2 y = yl[q];
-                if (col < n && q < ch.nq) {
-                    HS_GLOBAL TO* const dst = uout + (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col;
-                    if (MODE == MODE_BWD) y = csub<float>(ccast<float, double>(ld2(dst)), y);
-                    gst(dst, cvt_out<TO, float>(y));
-                }
-                gs[cc * RQ + q] = y;
+                if (MODE == MODE_BWD) y = csub<float>(uold[q], y);
+                if (col5 < n && q < ch.nq)
+                    gst(uout + (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col5, cvt_out<TO, float>(y));
+                gs[cc5 * RQ + q] = y;
             }
         }
         wave_sync();
@@ -441,7 +518,7 @@ bool launch_compress(int B, int seg, int prec, const ProbDev* probs, const CompD
 }
 
 size_t chainc_lds_bytes(int B, int seg, int rq, int waves) {
-    const int per = seg * rq + 4 * B * rq;
+    const int per = seg * rq + 4 * B * rq + 2 * B * B;
     return (size_t)per * waves * sizeof(float2);
 }
 

@@ -47,32 +47,6 @@ __device__ __forceinline__ void wg_barrier() {
 // first LU step of physical segment s (columns s*SEG+1 .. s*SEG+SEG) of a strip with column direction cd
 __host__ __device__ __forceinline__ int seg_tbase(int cd, int n, int s) { return cd > 0 ? s * SEG : n - s * SEG - SEG; }
 
-// acc += l * z_k for complex values, where z_k is lane k of this lane's 16-lane row (DPP row
-// broadcast as the first operand of each fused multiply-add: no LDS round trip for the vector).  The
-// leading s_nop covers the two wait states between a VALU write of z and its read through DPP.  Not
-// volatile: the compiler may schedule the loads of l ahead of it.
-template <int K>
-__device__ __forceinline__ void cfma_rowbcast(float& ax, float& ay, float lx, float ly, float zx, float zy) {
-    asm("s_nop 1\n\t"
-        "v_fmac_f32_dpp %0, %4, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, -%5, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %5, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %4, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
-        : "+v"(ax), "+v"(ay)
-        : "v"(lx), "v"(ly), "v"(zx), "v"(zy), "i"(K));
-}
-// The same product starting a sum: acc = l * z_k (no zeroed accumulators to initialise).
-template <int K>
-__device__ __forceinline__ void cmul_rowbcast(float& ax, float& ay, float lx, float ly, float zx, float zy) {
-    asm("s_nop 1\n\t"
-        "v_mul_f32_dpp %0, %4, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, -%5, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_mul_f32_dpp %1, %5, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %4, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
-        : "=&v"(ax), "=&v"(ay)
-        : "v"(lx), "v"(ly), "v"(zx), "v"(zy), "i"(K));
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------

@@ -94,6 +94,32 @@ __device__ __forceinline__ void buf_st(double2 v, __amdgpu_buffer_rsrc_t r, uint
     __builtin_amdgcn_raw_buffer_store_b128(b, r, (int)voff, (int)soff, 0);
 }
 
+// acc += l * z_k for complex values, where z_k is lane k of this lane's 16-lane row (DPP row
+// broadcast as the first operand of each fused multiply-add: no LDS round trip for the vector).  The
+// leading s_nop covers the two wait states between a VALU write of z and its read through DPP.  Not
+// volatile: the compiler may schedule the loads of l ahead of it.
+template <int K>
+__device__ __forceinline__ void cfma_rowbcast(float& ax, float& ay, float lx, float ly, float zx, float zy) {
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %4, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%5, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %5, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
+        : "+v"(ax), "+v"(ay)
+        : "v"(lx), "v"(ly), "v"(zx), "v"(zy), "i"(K));
+}
+// The same product starting a sum: acc = l * z_k (no zeroed accumulators to initialise).
+template <int K>
+__device__ __forceinline__ void cmul_rowbcast(float& ax, float& ay, float lx, float ly, float zx, float zy) {
+    asm("s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %4, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%5, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %5, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
+        : "=&v"(ax), "=&v"(ay)
+        : "v"(lx), "v"(ly), "v"(zx), "v"(zy), "i"(K));
+}
+
 // prefetch distance in ticks: as deep as the register budget of one wave allows
 template <class T, int BS> struct Ring { static constexpr int D = (sizeof(T) == 8 || BS > 17) ? 2 : 4; };
 
