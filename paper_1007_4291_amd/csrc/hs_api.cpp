@@ -629,10 +629,14 @@ static std::vector<ChainDev> seg_table(const std::vector<int>& n, const std::vec
     return ch;
 }
 
-// Right-hand sides per compressed-chain workgroup (HELM_CRQ = 4 or 8; default 8).
+// Right-hand sides per compressed-chain workgroup (HELM_CRQ = 4 or 8; default 4).
 static int crq_env() {
     const char* e = std::getenv("HELM_CRQ");
-    return (e && std::atoi(e) == 4) ? 4 : 8;
+    return (e && std::atoi(e) == 8) ? 8 : 4;
+}
+// The group size to use for `waves` segments: 8 only where its LDS fits one workgroup.
+static int fit_crq(int B, int cseg, int waves, int want) {
+    return (want == 8 && chainc_lds_bytes(B, cseg, 8, std::max(waves, 4)) <= 160 * 1024) ? 8 : 4;
 }
 
 // Chain kernel kind: HELM_SWEEP_SEG = 0 / 1 forces the plain / segmented chains, HELM_SWEEP_KIND = 0 / 1 /
@@ -667,8 +671,8 @@ static SoloPlan solo_plan(const sweep_factors_t M, int nrhs) {
         P.segws_bytes = compute_elem(M->prec) * (size_t)seg_ws_elems((int)P.sc.size(), P.seg_wg);
     }
     if (M->comp) {
-        P.crq = crq_env();
         P.cwaves = (n + M->cseg - 1) / M->cseg;
+        P.crq = fit_crq(B, M->cseg, P.cwaves, crq_env());
         for (int g = 0; g * P.crq < nrhs; ++g)
             for (int f = 0; f < 2; ++f)
                 P.cc.push_back(ChainDev{0, f, g * P.crq, std::min(P.crq, nrhs - g * P.crq), g * P.crq, 0, 0});
@@ -937,8 +941,9 @@ static int build_comp_table(helm_batch_t b, int crq) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->A[a]->n > b->A[c]->n; });
     std::vector<ChainDev> cc;
     int w = 1;
+    for (int p : order) w = std::max(w, (b->A[p]->n + b->cseg - 1) / b->cseg);
+    crq = fit_crq(b->B, b->cseg, w, crq);
     for (int p : order) {
-        w = std::max(w, (b->A[p]->n + b->cseg - 1) / b->cseg);
         for (int g = 0; g * crq < b->nrhs[p]; ++g)
             for (int f = 0; f < 2; ++f)
                 cc.push_back(ChainDev{p, f, g * crq, std::min(crq, b->nrhs[p] - g * crq), base[p] + g * crq, 0, 0});
@@ -1323,6 +1328,7 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
             b->kind = 2;
             for (int crq : {8, 4}) {
                 if ((rc = build_comp_table(b, crq))) break;
+                if (b->crq != crq) continue;                  // 8 does not fit the workgroup's LDS
                 double per = 0;
                 if ((rc = time_one(&per))) break;
                 if (per < best) { best = per; best_kind = 2; best_crq = crq; best_segt = 0; }

@@ -47,9 +47,8 @@ template <int BS, int SEG> struct CompShape {
     static constexpr int O_G2 = O_G1 + SEG * R1P;
     static constexpr int O_G3 = O_G2 + BS * R2P;
     static constexpr int O_PHI = O_G3 + BS * R3P;    // Phi, row-major
-    static constexpr int O_PHIT = O_PHI + BS * BS;   // Phi^T, row-major
-    static constexpr int O_CPL = O_PHIT + BS * BS;   // [SEG][2]: layer-row couplings to the previous / next layer
-    static constexpr int SIZE = (O_CPL + 2 * SEG + 1) & ~1;
+    static constexpr int O_CPL = O_PHI + BS * BS;    // [SEG][2]: layer-row couplings to the previous / next layer
+    static constexpr int SIZE = (O_CPL + 2 * SEG + 1) & ~1;   // even: every block and section 16-byte aligned
 };
 
 template <int BS, int SEG> __host__ __device__ constexpr bool comp_valid() {
@@ -179,12 +178,9 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
         } else if (e < SH::O_PHI) {
             const int k = (e - SH::O_G3) / SH::R3P, jj = (e - SH::O_G3) - k * SH::R3P;
             if (jj < SEG) v = zf(k, jj);                                // US[jj][k] = QF[k][jj]
-        } else if (e < SH::O_PHIT) {
+        } else if (e < SH::O_CPL) {
             const int r = (e - SH::O_PHI) / BS, k = (e - SH::O_PHI) - r * BS;
             v = zf(r, SEG + k);                                         // Phi[r][k]
-        } else if (e < SH::O_CPL) {
-            const int r = (e - SH::O_PHIT) / BS, k = (e - SH::O_PHIT) - r * BS;
-            v = zf(k, SEG + r);                                         // Phi^T[r][k]
         } else if (e < SH::O_CPL + 2 * SEG) {
             const int q = e - SH::O_CPL;
             v = cpl[q >> 1][q & 1];
@@ -198,13 +194,34 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
 // physical segment of the strips
 // ---------------------------------------------------------------------------------------------
 template <int BS, int SEG, int RQ> struct ChainCShape {
-    // LDS (complex64), per segment: gamma / layer row by column, qf, qb, c_in, x_above, and the strip's
-    // Phi and Phi^T of the segment (staged for the spines)
+    // LDS (complex64), per segment: gamma / layer row by column, qf, qb, c_in, x_above, the strip's Phi,
+    // and a staging area that holds G2, then G3.  Phi and the staging area are filled by asynchronous
+    // global-to-LDS copies in chunks of 128 values, so both are padded to whole chunks.
+    using SH = CompShape<BS, SEG>;
     static constexpr int GAM = SEG * RQ;
     static constexpr int VEC = BS * RQ;
-    static constexpr int PHI = BS * BS;
-    static constexpr int PER_SEG = GAM + 4 * VEC + 2 * PHI;
+    static constexpr int PHIP = (BS * BS + 127) & ~127;
+    static constexpr int STG = ((BS * SH::R2P > BS * SH::R3P ? BS * SH::R2P : BS * SH::R3P) + 127) & ~127;
+    static constexpr int PER_SEG = GAM + 4 * VEC + PHIP + STG;
+    static_assert(PHIP > BS * BS, "the spines' spare slot lies in the padding of the Phi area");
 };
+
+// Asynchronous copy of LEN complex64 values (LEN even, src 16-byte aligned) from global memory into this
+// wave's LDS area dst (room for LEN rounded up to 128): chunk u of lane l moves values 128u + 2l and
+// 128u + 2l + 1 (one 16-byte global-to-LDS load per lane and chunk, written at the lane's own 16 bytes of
+// the chunk).  Lanes past the end re-read the first pair, into the padding.  The data is in LDS once
+// vmcnt has drained (lds_stage_wait).
+template <int LEN>
+__device__ __forceinline__ void lds_stage(float2* dst, const HS_GLOBAL float2* src, int lane) {
+    constexpr int NCH = (LEN + 127) / 128;
+#pragma unroll
+    for (int u = 0; u < NCH; ++u) {
+        const int e = 128 * u + 2 * lane;
+        __builtin_amdgcn_global_load_lds((const HS_GLOBAL void*)(src + (e < LEN ? e : 0)),
+                                         (__attribute__((address_space(3))) void*)(dst + 128 * u), 16, 0, 0);
+    }
+}
+__device__ __forceinline__ void lds_stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 template <int BS, int SEG, int MODE, class TI, class TO, int RQ>
 __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
@@ -221,7 +238,8 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     float2* const qb = qf + nwv * LS::VEC;
     float2* const cin = qb + nwv * LS::VEC;
     float2* const xab = cin + nwv * LS::VEC;
-    float2* const phl = xab + nwv * LS::VEC;            // [nwv][2][BS][BS]: Phi, Phi^T of each segment
+    float2* const phl = xab + nwv * LS::VEC;            // [nwv][PHIP]: Phi of each segment, row-major
+    float2* const stg = phl + nwv * LS::PHIP;           // [nwv][STG]: G2, then G3, of each segment
 
     const ChainDev ch = chains[blockIdx.x];
     if (ch.nq == 0) return;
@@ -230,9 +248,13 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     const int n = P.n, cmid = P.c;
     const int L = ch.front == 0 ? P.L_lo : P.L_up;
     const int S = (n + SEG - 1) / SEG;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (wv >= S) {
-        // no segment for this wave: take part in the chain's barriers, then leave
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index: uniform
+    int lane = threadIdx.x & 63;      // made opaque at every strip (below): per-lane offsets are recomputed
+                                      // in the strip loop rather than held in registers across it
+    constexpr int NSW = RQ / 2;                        // spine waves (the launch has at least as many)
+    const bool segw = wv < S;                          // this wave has a segment of the strips
+    if (!segw && wv >= NSW) {
+        // neither a segment nor a spine for this wave: take part in the chain's barriers, then leave
         for (int b = 0; b < 4 * L; ++b) __syncthreads();
         return;
     }
@@ -247,235 +269,261 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     const int s = wv;
     constexpr int NQH = 64 / SEG;                      // right-hand-side lanes per column in the input step
     float2* const gs = gam + s * LS::GAM;
+    float2* const stg_s = stg + s * LS::STG;
 
-    // A spine (one wave): v <- Mat_ss v + add_ss over the segments ss in LU order (up) or reverse LU
-    // order, storing the value entering each segment in store[ss]; Mat = Phi (mat 0) or Phi^T (mat 1).
-    // Lane (r, q): row r < BS of right-hand side q (and q + 4 for 8 per workgroup); the rows of 16 lanes
-    // are the right-hand sides, so the other rows' values come by DPP row broadcast, and the matrix
-    // row of the next step is read from LDS while this step's products run.
+    // A spine: v <- Mat_ss v + add_ss over the segments ss in LU order (up) or reverse LU order, storing
+    // the value entering each segment in store[ss]; Mat = Phi (mat 0) or Phi^T (mat 1).  Waves
+    // 0 .. RQ/2 - 1 take two right-hand sides each.  Lane (half, p, r) = (lane >> 5, (lane >> 4) & 1,
+    // lane & 15) holds row r of right-hand side q = 2 wv + p and sums Mat[r][kk] v[kk] over its half of the
+    // terms, kk = KH half + j (j < KH): v[kk] comes by DPP row broadcast from lane j of a copy of v that is
+    // rotated by KH lanes in the upper half, and the two halves are added across lanes l and l ^ 32.  The
+    // next segment's matrix row and addends are read from LDS at the top of each step, under its products.
     auto spine = [&](int mat, bool up, const float2* addv, float2* store) __attribute__((always_inline)) {
-        constexpr int H = RQ / 4;
-        const int sr = lane & 15, sq = lane >> 4, srr = sr < BS ? sr : BS - 1;
-        float2 v[H];
-#pragma unroll
-        for (int h = 0; h < H; ++h) v[h] = make_float2(0.f, 0.f);
+        constexpr int KH = (BS + 1) / 2;
+        constexpr int NA = 2;                           // independent partial sums
+        const int r = lane & 15, half = lane >> 5, q = 2 * wv + ((lane >> 4) & 1);
+        const int rr = r < BS ? r : BS - 1, kk0 = KH * half;
         auto seg_at = [&](int k) { return up ? k : S - 1 - k; };
-        float2 pr[BS];
-        {
-            const float2* const pb = phl + seg_at(0) * 2 * LS::PHI + mat * LS::PHI + srr * BS;
+        // Mat[r][kk0 + j] of segment ss at pbase + ss * PHIP + j * pstep.  Past the block (kk0 + j >= BS)
+        // this reads finite values of the padded Phi area (every entry of it is written by the strip's
+        // copy, or is the spare slot), and they multiply rows of v that are zero.
+        const float2* const pbase = phl + (mat == 0 ? rr * BS + kk0 : rr + kk0 * BS);
+        const int pstep = mat == 0 ? 1 : BS;
+        static_assert((BS - 1) + (2 * ((BS + 1) / 2) - 1) * BS < LS::PHIP, "row reads stay in the Phi area");
+        auto load_row = [&](int ss, float2 (&dst)[KH]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int kk = 0; kk < BS; ++kk) pr[kk] = pb[kk];
-        }
-        for (int k = 0; k < S; ++k) {
-            const int ss = seg_at(k);
-            float2 ad[H];
+            for (int j = 0; j < KH; ++j) dst[j] = pbase[ss * LS::PHIP + j * pstep];
+        };
+        float2 v = make_float2(0.f, 0.f), ad, pr[KH], pr2[KH];
+        load_row(seg_at(0), pr);
+        ad = addv[(seg_at(0) * BS + rr) * RQ + q];
+        // lanes that store nothing (upper half, rows past the block) write a spare slot: the padding of
+        // segment 0's Phi area
+        float2* const spare = phl + BS * BS;
+        auto step = [&](int k, float2 (&cur)[KH], float2 (&nxt)[KH]) __attribute__((always_inline)) {
+            const int ss = seg_at(k), sn = seg_at(k + 1 < S ? k + 1 : k);
+            load_row(sn, nxt);
+            const float2 adn = addv[(sn * BS + rr) * RQ + q];
+            __builtin_amdgcn_sched_barrier(0);
+            // the upper half's copy of v, rotated so that lane j holds v[KH + j] (row_ror by 16 - KH)
+            float2 vr;
+            vr.x = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v.x), __float_as_int(v.x),
+                                                              0x120 + (16 - KH), 0xC, 0xF, false));
+            vr.y = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v.y), __float_as_int(v.y),
+                                                              0x120 + (16 - KH), 0xC, 0xF, false));
+            float ax[NA], ay[NA];
+            static_for<KH>([&](auto KC) __attribute__((always_inline)) {
+                constexpr int j = decltype(KC)::value, a = j % NA;
+                if constexpr (j < NA) cmul_rowbcast<j>(ax[a], ay[a], cur[j].x, cur[j].y, vr.x, vr.y);
+                else cfma_rowbcast<j>(ax[a], ay[a], cur[j].x, cur[j].y, vr.x, vr.y);
+            });
+            asm volatile("" ::"v"(v.x), "v"(v.y));     // v stays live: its rotated copy takes new registers
+            float sx = ax[0], sy = ay[0];
 #pragma unroll
-            for (int h = 0; h < H; ++h) ad[h] = addv[(ss * BS + srr) * RQ + sq + 4 * h];
-            if (sr < BS) {
-#pragma unroll
-                for (int h = 0; h < H; ++h) store[(ss * BS + sr) * RQ + sq + 4 * h] = v[h];
+            for (int a = 1; a < NA; ++a) {
+                if (a < KH) { sx += ax[a]; sy += ay[a]; }
             }
-            float2 nv[H];
-#pragma unroll
-            for (int h = 0; h < H; ++h) {
-                float a0x, a0y, a1x, a1y;
-                static_for<BS>([&](auto KC) __attribute__((always_inline)) {
-                    constexpr int kk = decltype(KC)::value;
-                    if constexpr (kk == 0) cmul_rowbcast<kk>(a0x, a0y, pr[kk].x, pr[kk].y, v[h].x, v[h].y);
-                    else if constexpr (kk == 1) cmul_rowbcast<kk>(a1x, a1y, pr[kk].x, pr[kk].y, v[h].x, v[h].y);
-                    else if constexpr (kk & 1) cfma_rowbcast<kk>(a1x, a1y, pr[kk].x, pr[kk].y, v[h].x, v[h].y);
-                    else cfma_rowbcast<kk>(a0x, a0y, pr[kk].x, pr[kk].y, v[h].x, v[h].y);
-                });
-                if constexpr (BS == 1) { a1x = 0.f; a1y = 0.f; }
-                nv[h] = sr < BS ? make_float2(ad[h].x + (a0x + a1x), ad[h].y + (a0y + a1y)) : make_float2(0.f, 0.f);
-            }
-            if (k + 1 < S) {
-                const float2* const pb = phl + seg_at(k + 1) * 2 * LS::PHI + mat * LS::PHI + srr * BS;
-#pragma unroll
-                for (int kk = 0; kk < BS; ++kk) pr[kk] = pb[kk];
-            }
-#pragma unroll
-            for (int h = 0; h < H; ++h) v[h] = nv[h];
+            sx = xor_sum<32>(sx);
+            sy = xor_sum<32>(sy);
+            v = r < BS ? make_float2(ad.x + sx, ad.y + sy) : make_float2(0.f, 0.f);
+            ad = adn;
+            // the value entering the next segment, stored now: its register is not rewritten until the
+            // end of the next step, so the store never holds up a step
+            if (k + 1 < S) *(half == 0 && r < BS ? &store[(sn * BS + r) * RQ + q] : spare) = v;
+        };
+        *(half == 0 && r < BS ? &store[(seg_at(0) * BS + r) * RQ + q] : spare) = v;
+        for (int k = 0; k < S; k += 2) {       // two steps per pass: the row buffers swap roles, no copies
+            step(k, pr, pr2);
+            if (k + 1 < S) step(k + 1, pr2, pr);
         }
     };
 
-    // Global data of a strip is requested in few round trips: its gamma columns G1, input row and
-    // layer-row couplings together at the start of the strip, the backward phase's output row during the
-    // backward spine, G2 and G3 all at once where they are used.
+    // Global data of a strip is requested in three groups, each a phase ahead of its use: after the
+    // previous strip's backward spine its couplings, input row, Phi (straight to LDS) and the gamma columns
+    // G1 (in the order they are consumed), which arrive during the previous strip's phase 5; after phase 1
+    // the c_in block G2 (straight to LDS), which arrives during the forward spine; after phase 3 the
+    // x_above block G3 (to LDS, in G2's place) and, backward, the output row, which arrive during the
+    // backward spine.  Every group issues a fixed number of loads (masked lanes read a valid address), so
+    // that a wait for "all but the next strip's first group" is an exact vmcnt.
     auto strip_of = [&](int i) { return MODE == MODE_FWD ? i + 1 : L - i; };     // strip index in its front
     auto strip_blk = [&](int i) -> const HS_GLOBAL float2* {
         return cmp + ((int64_t)(sbase + strip_of(i) - 1) * S + s) * SH::SIZE;
     };
     constexpr int NH0 = RQ / NQH;                      // input values per lane
-    const int icc = lane % SEG, iqh = lane / SEG;      // input step: this lane's column and right-hand sides
-    float2 g1[SEG];
-    double2 fin_v[NH0];                                 // forward phase: f on the next strip's layer row
-    float2 cpl_v;                                       // the next strip's coupling at this lane's column
-    auto prefetch_strip = [&](int i) __attribute__((always_inline)) {
-        const HS_GLOBAL float2* const b = strip_blk(i);
-        const HS_GLOBAL float2* const b1 = b + SH::O_G1 + (lane < SH::R1P ? lane : 0);
-#pragma unroll
-        for (int j = 0; j < SEG; ++j) g1[j] = gld(b1 + j * SH::R1P);
+    int icc, iqh, jj5, l3r;                            // input step: this lane's column and right-hand sides;
+    bool l3;                                           // phase 3 / 5: rows B .. R1 of G2 (qb, then y), 2B .. R1 of G3
+    auto lane_roles = [&]() __attribute__((always_inline)) {
+        icc = lane % SEG;
+        iqh = lane / SEG;
+        l3 = lane >= BS && lane < SH::R1;
+        jj5 = lane >= 2 * BS && lane < SH::R1 ? lane - 2 * BS : 0;
+        l3r = l3 ? lane - BS : 0;
+    };
+    lane_roles();
+    constexpr int NREQ = 1 + (MODE == MODE_FWD ? NH0 : 0) + (BS * BS + 127) / 128 + SEG;   // loads of a first group
+    float2 cpl_v, g1[SEG];
+    double2 fin_v[NH0];
+    // the first group of strip i (i < L)
+    auto request = [&](int i) __attribute__((always_inline)) {
         const int st = strip_of(i), cd = (st & 1) ? -1 : 1;
-        const int j = cd > 0 ? icc : SEG - 1 - icc;
-        cpl_v = gld(b + SH::O_CPL + 2 * j + (MODE == MODE_FWD ? 0 : 1));
+        const HS_GLOBAL float2* const blk = strip_blk(i);
+        // the block through a buffer resource: wave-uniform base, per-lane 32-bit offsets (no 64-bit
+        // address registers)
+        const __amdgpu_buffer_rsrc_t rs = buf_rsrc(blk, SH::SIZE * (uint32_t)sizeof(float2));
+        buf_ld(cpl_v, rs, (uint32_t)(SH::O_CPL + 2 * (cd > 0 ? icc : SEG - 1 - icc) + (MODE == MODE_FWD ? 0 : 1)) * 8u, 0u);
         if constexpr (MODE == MODE_FWD) {
             const int jl = jF + dirF * st, col = s * SEG + icc;
 #pragma unroll
             for (int h = 0; h < NH0; ++h) {
                 const int q = iqh + NQH * h;
-                fin_v[h] = (col < n && q < ch.nq)
-                               ? ld2(fin + (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col)
-                               : make_double2(0.0, 0.0);
+                const bool ok = col < n && q < ch.nq;
+                const double2 f = ld2(fin + (ok ? (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col : (int64_t)0));
+                fin_v[h] = ok ? f : make_double2(0.0, 0.0);
             }
         }
+        lds_stage<BS * BS>(phl + s * LS::PHIP, blk + SH::O_PHI, lane);
+        const uint32_t v1 = (uint32_t)(SH::O_G1 + (lane < SH::R1P ? lane : 0)) * 8u;
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) buf_ld(g1[j], rs, v1, (uint32_t)(j * SH::R1P) * 8u);
     };
+    if (segw) request(0);
     for (int i = 0; i < L; ++i) {
-        prefetch_strip(i);      // G1, the input row and couplings together: one memory latency per strip
+        asm volatile("" : "+v"(lane));
+        lane_roles();
         const int st = strip_of(i);                            // strip index in its front (1..L)
         const int jl = jF + dirF * st;                         // layer row
         const int cd = (st & 1) ? -1 : 1;                      // column direction of its block LU
         const HS_GLOBAL float2* const blk = strip_blk(i);
-        // ---- 0. the strip's layer-row input on this segment's columns
-        {
-            const int col = s * SEG + icc;
-#pragma unroll
-            for (int h = 0; h < NH0; ++h) {
-                const int q = iqh + NQH * h;
-                float2 g = make_float2(0.f, 0.f);
-                if (col < n && q < ch.nq) {
-                    const int64_t rb = (int64_t)(ch.rhs0 + q) * N;
-                    if (MODE == MODE_FWD) {
-                        const float2 yp = i == 0 ? ccast<float, double>(ld2(uout + rb + (int64_t)(jl - dirF - 1) * n + col))
-                                                 : gs[icc * RQ + q];
-                        g = csub<float>(make_float2((float)fin_v[h].x, (float)fin_v[h].y), cmul<float>(cpl_v, yp));
-                    } else {
-                        const float2 yn = i == 0 ? ccast<float, double>(ld2(uout + rb + (int64_t)(cmid - 1) * n + col))
-                                                 : gs[icc * RQ + q];
-                        g = cmul<float>(cpl_v, yn);
-                    }
-                }
-                gs[icc * RQ + q] = g;
-            }
-        }
-        wave_sync();
-        // ---- 1. qf, qb and the local part of y from gamma; meanwhile this segment's Phi and Phi^T go to
-        // LDS for the spines
-        constexpr int NPH = (2 * BS * BS + 63) / 64;
-        {
-            float2 acc[RQ];
-#pragma unroll
-            for (int q = 0; q < RQ; ++q) acc[q] = make_float2(0.f, 0.f);
-            // in groups of 2 columns, so that only one group's gamma values are in flight from LDS
-            static_for<SEG / 2>([&](auto GC) __attribute__((always_inline)) {
-                static_for<2>([&](auto UC) __attribute__((always_inline)) {
-                    constexpr int j = 2 * decltype(GC)::value + decltype(UC)::value;
-                    const int cc = cd > 0 ? j : SEG - 1 - j;
-#pragma unroll
-                    for (int q = 0; q < RQ; ++q) acc[q] = cfma<float>(g1[j], gs[cc * RQ + q], acc[q]);
-                });
-                __builtin_amdgcn_sched_barrier(0);
-            });
-            wave_sync();          // every lane has read gamma: the layer-row values y take its place
-            if (lane < BS) {
-#pragma unroll
-                for (int q = 0; q < RQ; ++q) qf[(s * BS + lane) * RQ + q] = acc[q];
-            } else if (lane < 2 * BS) {
-#pragma unroll
-                for (int q = 0; q < RQ; ++q) qb[(s * BS + lane - BS) * RQ + q] = acc[q];
-            } else if (lane < SH::R1) {
-                const int jj = lane - 2 * BS, cc = cd > 0 ? jj : SEG - 1 - jj;
-#pragma unroll
-                for (int q = 0; q < RQ; ++q) gs[cc * RQ + q] = acc[q];
-            }
-        }
-        {
-            float2 phr[NPH];
-#pragma unroll
-            for (int u = 0; u < NPH; ++u) {
-                const int e = lane + 64 * u;
-                phr[u] = gld(blk + SH::O_PHI + (e < 2 * BS * BS ? e : 0));   // Phi then Phi^T, contiguous
-            }
-#pragma unroll
-            for (int u = 0; u < NPH; ++u) {
-                const int e = lane + 64 * u;
-                if (e < 2 * BS * BS) phl[s * 2 * LS::PHI + e] = phr[u];
-            }
-        }
-        __syncthreads();
-        // ---- 2. forward spine (wave 0): carries entering every segment, in the strip's LU order
-        if (wv == 0) spine(0, cd > 0, qf, cin);
-        __syncthreads();
-        // ---- 3. qb += W c_in, y += VS c_in
-        if (lane >= BS && lane < SH::R1) {
-            // G2 entries of this lane (rows B .. R1 of the c_in block), all requested at once
-            float2 g2[BS];
-#pragma unroll
-            for (int k = 0; k < BS; ++k) g2[k] = gld(blk + SH::O_G2 + k * SH::R2P + lane - BS);
-            float2 acc[RQ];
-#pragma unroll
-            for (int q = 0; q < RQ; ++q) acc[q] = make_float2(0.f, 0.f);
-            static_for<(BS + 3) / 4>([&](auto GC) __attribute__((always_inline)) {
-                static_for<4>([&](auto UC) __attribute__((always_inline)) {
-                    constexpr int k = 4 * decltype(GC)::value + decltype(UC)::value;
-                    if constexpr (k < BS) {
-#pragma unroll
-                        for (int q = 0; q < RQ; ++q) acc[q] = cfma<float>(g2[k], cin[(s * BS + k) * RQ + q], acc[q]);
-                    }
-                });
-                __builtin_amdgcn_sched_barrier(0);
-            });
-            float2* const d = lane < 2 * BS ? &qb[(s * BS + lane - BS) * RQ]
-                                            : &gs[(cd > 0 ? lane - 2 * BS : SEG - 1 - (lane - 2 * BS)) * RQ];
-#pragma unroll
-            for (int q = 0; q < RQ; ++q) d[q] = cadd<float>(d[q], acc[q]);
-        }
-        // G3 entries of this lane (the x_above block) and, in the backward phase, the current values of the
-        // output row, requested before the backward spine
-        const int jj5 = lane >= 2 * BS && lane < SH::R1 ? lane - 2 * BS : 0;
+        // phase 3 / 5: this lane's row of the y block and its column
         const int cc5 = cd > 0 ? jj5 : SEG - 1 - jj5;
         const int col5 = s * SEG + cc5;
         const bool out5 = lane >= 2 * BS && lane < SH::R1 && col5 < n;
         float2 uold[MODE == MODE_BWD ? RQ : 1];
-        if constexpr (MODE == MODE_BWD) {
-#pragma unroll
-            for (int q = 0; q < RQ; ++q)
-                uold[q] = (out5 && q < ch.nq)
-                              ? ccast<float, double>(ld2(uout + (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col5))
-                              : make_float2(0.f, 0.f);
-        }
-        __syncthreads();
-        // ---- 4. backward spine (wave 0): values entering every segment from above, reverse LU order
-        if (wv == 0) spine(1, cd < 0, qb, xab);
-        __syncthreads();
-        // ---- 5. y += US x_above; the strip's layer-row output
-        if (lane >= 2 * BS && lane < SH::R1) {
-            float2 g3[BS];
-#pragma unroll
-            for (int k = 0; k < BS; ++k) g3[k] = gld(blk + SH::O_G3 + k * SH::R3P + jj5);
-            float2 yl[RQ];
-#pragma unroll
-            for (int q = 0; q < RQ; ++q) yl[q] = gs[cc5 * RQ + q];
-            static_for<(BS + 3) / 4>([&](auto GC) __attribute__((always_inline)) {
-                static_for<4>([&](auto UC) __attribute__((always_inline)) {
-                    constexpr int k = 4 * decltype(GC)::value + decltype(UC)::value;
-                    if constexpr (k < BS) {
-#pragma unroll
-                        for (int q = 0; q < RQ; ++q) yl[q] = cfma<float>(g3[k], xab[(s * BS + k) * RQ + q], yl[q]);
+        if (segw) {
+            // ---- 0. the strip's layer-row input on this segment's columns
+            {
+                const int col = s * SEG + icc;
+    #pragma unroll
+                for (int h = 0; h < NH0; ++h) {
+                    const int q = iqh + NQH * h;
+                    float2 g = make_float2(0.f, 0.f);
+                    if (col < n && q < ch.nq) {
+                        const int64_t rb = (int64_t)(ch.rhs0 + q) * N;
+                        if (MODE == MODE_FWD) {
+                            const float2 yp = i == 0 ? ccast<float, double>(ld2(uout + rb + (int64_t)(jl - dirF - 1) * n + col))
+                                                     : gs[icc * RQ + q];
+                            g = csub<float>(make_float2((float)fin_v[h].x, (float)fin_v[h].y), cmul<float>(cpl_v, yp));
+                        } else {
+                            const float2 yn = i == 0 ? ccast<float, double>(ld2(uout + rb + (int64_t)(cmid - 1) * n + col))
+                                                     : gs[icc * RQ + q];
+                            g = cmul<float>(cpl_v, yn);
+                        }
                     }
+                    gs[icc * RQ + q] = g;
+                }
+            }
+            wave_sync();
+            // ---- 1. qf, qb and the local part of y from gamma
+            {
+                float2 acc[RQ];
+    #pragma unroll
+                for (int q = 0; q < RQ; ++q) acc[q] = make_float2(0.f, 0.f);
+                // in groups of 2 columns, so that only one group's gamma values are in flight from LDS
+                static_for<SEG / 2>([&](auto GC) __attribute__((always_inline)) {
+                    static_for<2>([&](auto UC) __attribute__((always_inline)) {
+                        constexpr int j = 2 * decltype(GC)::value + decltype(UC)::value;
+                        const int cc = cd > 0 ? j : SEG - 1 - j;
+    #pragma unroll
+                        for (int q = 0; q < RQ; ++q) acc[q] = cfma<float>(g1[j], gs[cc * RQ + q], acc[q]);
+                    });
+                    __builtin_amdgcn_sched_barrier(0);
                 });
-                __builtin_amdgcn_sched_barrier(0);
-            });
-#pragma unroll
-            for (int q = 0; q < RQ; ++q) {
-                float2 y = yl[q];
-                if (MODE == MODE_BWD) y = csub<float>(uold[q], y);
-                if (col5 < n && q < ch.nq)
-                    gst(uout + (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col5, cvt_out<TO, float>(y));
-                gs[cc5 * RQ + q] = y;
+                // Phi is in LDS (it was requested before G1, all of which has been used); then the c_in block,
+                // to arrive during the forward spine
+                lds_stage_wait();
+                lds_stage<BS * SH::R2P>(stg_s, blk + SH::O_G2, lane);
+                wave_sync();          // every lane has read gamma: the layer-row values y take its place
+                if (lane < BS) {
+    #pragma unroll
+                    for (int q = 0; q < RQ; ++q) qf[(s * BS + lane) * RQ + q] = acc[q];
+                } else if (lane < 2 * BS) {
+    #pragma unroll
+                    for (int q = 0; q < RQ; ++q) qb[(s * BS + lane - BS) * RQ + q] = acc[q];
+                } else if (lane < SH::R1) {
+                    const int jj = lane - 2 * BS, cc = cd > 0 ? jj : SEG - 1 - jj;
+    #pragma unroll
+                    for (int q = 0; q < RQ; ++q) gs[cc * RQ + q] = acc[q];
+                }
             }
         }
-        wave_sync();
+        __syncthreads();
+        // ---- 2. forward spine (waves 0 .. NSW - 1): carries entering every segment, in the strip's LU order
+        if (wv < NSW) spine(0, cd > 0, qf, cin);
+        __syncthreads();
+        if (segw) {
+            // ---- 3. qb += W c_in, y += VS c_in
+            lds_stage_wait();
+            if (l3) {
+                float2 acc[RQ];
+    #pragma unroll
+                for (int q = 0; q < RQ; ++q) acc[q] = make_float2(0.f, 0.f);
+                // rolled: the broadcast c_in values are read from LDS step by step, not all at once
+    #pragma unroll 2
+                for (int k = 0; k < BS; ++k) {
+                    const float2 gk = stg_s[k * SH::R2P + l3r];
+    #pragma unroll
+                    for (int q = 0; q < RQ; ++q) acc[q] = cfma<float>(gk, cin[(s * BS + k) * RQ + q], acc[q]);
+                }
+                float2* const d = lane < 2 * BS ? &qb[(s * BS + lane - BS) * RQ]
+                                                : &gs[(cd > 0 ? lane - 2 * BS : SEG - 1 - (lane - 2 * BS)) * RQ];
+    #pragma unroll
+                for (int q = 0; q < RQ; ++q) d[q] = cadd<float>(d[q], acc[q]);
+            }
+            // the x_above block G3 and, in the backward phase, the current values of the output row, to arrive
+            // during the backward spine
+            wave_sync();              // every lane of the wave has read G2: G3 takes its place
+            lds_stage<BS * SH::R3P>(stg_s, blk + SH::O_G3, lane);
+            if constexpr (MODE == MODE_BWD) {
+    #pragma unroll
+                for (int q = 0; q < RQ; ++q) {
+                    const bool ok = out5 && q < ch.nq;
+                    const float2 u = ccast<float, double>(
+                        ld2(uout + (ok ? (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col5 : (int64_t)0)));
+                    uold[q] = ok ? u : make_float2(0.f, 0.f);
+                }
+            }
+        }
+        __syncthreads();
+        // ---- 4. backward spine (waves 0 .. NSW - 1): values entering every segment from above, reverse LU order
+        if (wv < NSW) spine(1, cd < 0, qb, xab);
+        __syncthreads();
+        if (segw) {
+            // ---- the next strip's first group (the last strip re-requests its own: a fixed count)
+            request(i + 1 < L ? i + 1 : i);
+            // ---- 5. y += US x_above; the strip's layer-row output
+            asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NREQ) : "memory");   // G3 (and the output row) have landed
+            if (lane >= 2 * BS && lane < SH::R1) {
+                float2 yl[RQ];
+    #pragma unroll
+                for (int q = 0; q < RQ; ++q) yl[q] = gs[cc5 * RQ + q];
+                // rolled: the broadcast x_above values are read from LDS step by step, not all at once
+    #pragma unroll 1
+                for (int k = 0; k < BS; ++k) {
+                    const float2 gk = stg_s[k * SH::R3P + jj5];
+    #pragma unroll
+                    for (int q = 0; q < RQ; ++q) yl[q] = cfma<float>(gk, xab[(s * BS + k) * RQ + q], yl[q]);
+                }
+    #pragma unroll
+                for (int q = 0; q < RQ; ++q) {
+                    float2 y = yl[q];
+                    if (MODE == MODE_BWD) y = csub<float>(uold[q], y);
+                    if (col5 < n && q < ch.nq)
+                        gst(uout + (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col5, cvt_out<TO, float>(y));
+                    gs[cc5 * RQ + q] = y;
+                }
+            }
+            wave_sync();
+        }
     }
 }
 
@@ -518,7 +566,11 @@ bool launch_compress(int B, int seg, int prec, const ProbDev* probs, const CompD
 }
 
 size_t chainc_lds_bytes(int B, int seg, int rq, int waves) {
-    const int per = seg * rq + 4 * B * rq + 2 * B * B;
+    // ChainCShape<B, seg, rq>::PER_SEG per wave
+    const int r2p = (B + seg + 15) & ~15, r3p = (seg + 15) & ~15;
+    const int phip = (B * B + 127) & ~127;
+    const int stg = ((B * r2p > B * r3p ? B * r2p : B * r3p) + 127) & ~127;
+    const int per = seg * rq + 4 * B * rq + phip + stg;
     return (size_t)per * waves * sizeof(float2);
 }
 
@@ -556,6 +608,7 @@ bool launch_chains_comp(int B, int seg, int rq, int in_prec, int out_prec, int p
                         const ChainDev* chains, int nchains, const IoDev* io, IoDev io_val, int waves,
                         const int32_t* active, hipStream_t s) {
     if (nchains <= 0) return true;
+    waves = std::max(waves, rq / 2);                   // the spines take rq / 2 waves
     if (!chainc_supported(B, seg) || waves < 1 || waves > 16) return false;
     if (chainc_lds_bytes(B, seg, rq, waves) > 160 * 1024) return false;
     if (in_prec == 0 && out_prec == 0)

@@ -102,8 +102,8 @@ template <int K>
 __device__ __forceinline__ void cfma_rowbcast(float& ax, float& ay, float lx, float ly, float zx, float zy) {
     asm("s_nop 1\n\t"
         "v_fmac_f32_dpp %0, %4, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, -%5, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %1, %5, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%5, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %1, %4, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
         : "+v"(ax), "+v"(ay)
         : "v"(lx), "v"(ly), "v"(zx), "v"(zy), "i"(K));
@@ -113,8 +113,8 @@ template <int K>
 __device__ __forceinline__ void cmul_rowbcast(float& ax, float& ay, float lx, float ly, float zx, float zy) {
     asm("s_nop 1\n\t"
         "v_mul_f32_dpp %0, %4, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, -%5, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
         "v_mul_f32_dpp %1, %5, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%5, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
         "v_fmac_f32_dpp %1, %4, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
         : "=&v"(ax), "=&v"(ay)
         : "v"(lx), "v"(ly), "v"(zx), "v"(zy), "i"(K));
