@@ -49,6 +49,12 @@ extern "C" {
 /* Precision of the stored factors and of the sweep arithmetic. */
 #define HELM_C128 0        /* complex128 factors, FP64 sweep                                  */
 #define HELM_C64 1         /* factors computed in FP64, stored as complex64, FP32 sweep        */
+/* Factors as HELM_C64; the sweep's block products Lambda_i^{-1} [B x R] (Algorithm 4) on the matrix
+ * cores in bf16x3 form (each FP32 operand split into bf16 hi + lo, three bf16 products, FP32
+ * accumulation: about 2^-16 relative error per product), 16 right-hand sides per wave, the strips'
+ * column recurrences as in the plain sweep; the middle layer on the FP32 vector path.  Accepted by
+ * sweep_factor only (the handle then reports HELM_C64 storage); B in {4, 5, 7, 9, 13, 17}. */
+#define HELM_C64_BF16X3 2
 
 typedef struct helm_problem_s* helm_problem_t;
 typedef struct sweep_factors_s* sweep_factors_t;
@@ -112,6 +118,8 @@ int helm_matvec(helm_problem_t A, const void* x, int32_t x_prec, void* y, int32_
  * 16-column segment of every front strip (the product of its steps' maps, a B x B block) is formed
  * from the stored factors as well; they serve only to apply the same M_alpha with a shorter
  * sequential path.
+ * With prec = HELM_C64_BF16X3 the complex64 factors are also kept split into bf16 hi / lo (the same
+ * size again, F / E / moving strips) for the matrix-core sweep.
  * Returns HELM_ESINGULAR if a block has a zero or non-finite pivot.  Synchronises `stream`. */
 int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_factors_t* out);
 

@@ -147,9 +147,9 @@ struct helm_problem_s {
 // table (groups of Q right-hand sides per front), the middle table (Qm per wave), the segmented chain
 // table where the segmented sweep applies, and the workspace sizes.
 struct SoloPlan {
-    std::vector<ChainDev> ch, md, sc, cc;
+    std::vector<ChainDev> ch, md, sc, cc, mc;
     int ks_chain = 1, ks_mid = 1, waves = 1, seg_wg = 0, kind = 0, cwaves = 0, crq = 8;
-    size_t spill_bytes = 0, segws_bytes = 0;
+    size_t spill_bytes = 0, segws_bytes = 0, mws_bytes = 0;
 };
 
 struct sweep_factors_s {
@@ -166,12 +166,16 @@ struct sweep_factors_s {
     DevBuf cmp, compw;
     int ncompw = 0, cseg = 0;
     bool comp = false;
+    // matrix-core chains (HELM_C64_BF16X3): split copy of the F / E / moving strips' blocks
+    bool mfma = false;
+    DevBuf msp;
     std::vector<SubDev> hsubs;
     std::vector<int> sub_rows;
     // single-problem chain tables (rebuilt when nrhs changes)
-    DevBuf chains, mids, segch, segws, cchains;
+    DevBuf chains, mids, segch, segws, cchains, mchains, mws;
+    int nmch = 0;
     int chains_nrhs = -1, nchains = 0, nmids = 0, ks_chain = 1, ks_mid = 1, waves = 1, ncch = 0, cwaves = 0, crq = 8;
-    int nsegch = 0, seg_wg = 0, kind = 0;   // kind 1: segmented chains, 2: compressed moving chains
+    int nsegch = 0, seg_wg = 0, kind = 0;   // kind 1: segmented chains, 2: compressed moving chains, 3: matrix-core chains
     helm_batch_t solo = nullptr;    // cached batch of one for fgmres_solve
     std::unique_ptr<SoloPlan> na_plan;   // host tables of the last sweep_apply_noalloc call
     int na_nrhs = -1;
@@ -206,6 +210,11 @@ struct helm_batch_s {
     DevBuf compw, cch;
     int ncompw = 0, ncch = 0, cwaves = 0, crq = 8, cseg = 0;
     bool comp = false;
+    // matrix-core chains (kind 3, factors HELM_C64_BF16X3): chain table (problem, front, 16 right-hand
+    // sides) and workspace
+    DevBuf mch, mws;
+    int nmch = 0;
+    bool mfma = false;
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // graph form of FGMRES: a restart cycle captured once (on its own stream) as a few graphs that are
@@ -394,9 +403,8 @@ static int factor_into(sweep_factors_t M, hipStream_t s) {
     const int n = A->n, B = A->B;
     HIPCHK(hipMemsetAsync(M->status.p, 0, sizeof(int), s));
     const ProbDev* pd = A->pd.as<ProbDev>();
-    (void)n;
     {
-        PhaseScope ph(PH_FACTOR, s, 2 + (M->seg ? 1 : 0) + (M->comp ? 1 : 0));
+        PhaseScope ph(PH_FACTOR, s, 2 + (M->seg ? 1 : 0) + (M->comp ? 1 : 0) + (M->mfma ? 1 : 0));
         if (!launch_factor(B, M->prec, pd, M->subs.as<SubDev>(), A->nsub - 1, M->status.as<int>(), s))
             return fail(HELM_EINVAL, "no factor kernel for B=%d", B);
         LAUNCHCHK();
@@ -413,6 +421,11 @@ static int factor_into(sweep_factors_t M, hipStream_t s) {
                 return fail(HELM_EINVAL, "no compression kernel for B=%d, segment width %d", B, M->cseg);
             LAUNCHCHK();
         }
+        if (M->mfma) {
+            if (!launch_msplit(B, M->fac.p, M->msp.p, (int64_t)(A->nsub - 1) * n, s))
+                return fail(HELM_EINVAL, "no split kernel for B=%d", B);
+            LAUNCHCHK();
+        }
     }
     int st = 0;
     HIPCHK(hipMemcpyAsync(&st, M->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -424,10 +437,15 @@ static int factor_into(sweep_factors_t M, hipStream_t s) {
 
 extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_factors_t* out) {
     if (!A || !out) return fail(HELM_EINVAL, "NULL argument");
-    if (prec != HELM_C128 && prec != HELM_C64) return fail(HELM_EINVAL, "prec must be HELM_C128 or HELM_C64");
+    if (prec != HELM_C128 && prec != HELM_C64 && prec != HELM_C64_BF16X3)
+        return fail(HELM_EINVAL, "prec must be HELM_C128, HELM_C64 or HELM_C64_BF16X3");
+    if (prec == HELM_C64_BF16X3 && !chainm_supported(A->B))
+        return fail(HELM_EINVAL, "HELM_C64_BF16X3 supports strip heights B in {4, 5, 7, 9, 13, 17} (B=%d)", A->B);
     hipStream_t s = (hipStream_t)stream;
     std::unique_ptr<sweep_factors_s> M(new sweep_factors_s());
     M->A = A;
+    M->mfma = prec == HELM_C64_BF16X3;
+    if (M->mfma) prec = HELM_C64;                       // storage: complex64 (plus the split copy)
     M->prec = prec;
     const int n = A->n, B = A->B;
     // stored column length (packed block + coupling scalars, padded to 16 bytes) per precision
@@ -442,6 +460,11 @@ extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_
         if ((rc = precheck_bytes((double)esz * (double)M->fac_elems + props, "the factor store"))) return rc;
     }
     if ((rc = M->fac.alloc(esz * (size_t)M->fac_elems))) return rc;
+    if (M->mfma) {
+        const double mb = (double)sizeof(float2) * (double)(A->nsub - 1) * n * pk;
+        if ((rc = precheck_bytes(mb, "the split copy of the factors"))) return rc;
+        if ((rc = M->msp.alloc((size_t)mb))) return rc;
+    }
     // strip descriptors: F, lower layers, E, upper layers (all height B), then the middle (2B-1).
     // Consecutive layers of a front alternate their column direction; jprev / jnext are the layer
     // rows before and after each layer in its front's sweep (the middle row after the last one).
@@ -482,7 +505,7 @@ extern "C" int sweep_factor(helm_problem_t A, int32_t prec, void* stream, sweep_
     if ((rc = M->status.alloc(sizeof(int)))) return rc;
     HIPCHK(hipMemcpy(M->subs.p, S.data(), sizeof(SubDev) * S.size(), hipMemcpyHostToDevice));
     // segmented sweep: propagators of every segment of every front strip (not the middle)
-    M->seg = seg_fits(prec == HELM_C128 ? 0 : 1, B, seg_waves_rhs(n), n);
+    M->seg = !M->mfma && seg_fits(prec == HELM_C128 ? 0 : 1, B, seg_waves_rhs(n), n);
     if (M->seg) {
         const int Sg = seg_count(n);
         const int64_t per_strip = seg_strip_elems(n, B);
@@ -678,6 +701,15 @@ static SoloPlan solo_plan(const sweep_factors_t M, int nrhs) {
                 P.cc.push_back(ChainDev{0, f, g * P.crq, std::min(P.crq, nrhs - g * P.crq), g * P.crq, 0, 0});
     }
     P.kind = pick_kind(M->seg, M->comp);
+    if (M->mfma) {
+        // matrix-core chains: one wave per (front, 16 right-hand sides), each with its own workspace
+        const int64_t per4 = chainm_ws_f4(n, B);
+        for (int g = 0; g * 16 < nrhs; ++g)
+            for (int f = 0; f < 2; ++f)
+                P.mc.push_back(ChainDev{0, f, g * 16, std::min(16, nrhs - g * 16), g * 16, 0, (int64_t)P.mc.size() * per4});
+        P.mws_bytes = sizeof(float) * 4 * (size_t)per4 * P.mc.size();
+        P.kind = 3;
+    }
     return P;
 }
 
@@ -714,6 +746,15 @@ static int ensure_solo_chains(sweep_factors_t M, int nrhs, hipStream_t s) {
         M->cwaves = P.cwaves;
         M->crq = P.crq;
     }
+    if (M->mfma) {
+        if ((rc = M->mchains.alloc(sizeof(ChainDev) * P.mc.size()))) return rc;
+        HIPCHK(hipMemcpy(M->mchains.p, P.mc.data(), sizeof(ChainDev) * P.mc.size(), hipMemcpyHostToDevice));
+        M->nmch = (int)P.mc.size();
+        if (M->mws.bytes < P.mws_bytes) {
+            if ((rc = precheck_bytes((double)P.mws_bytes, "the matrix-core chains' workspace"))) return rc;
+            if ((rc = M->mws.alloc(P.mws_bytes))) return rc;
+        }
+    }
     M->kind = P.kind;
     M->chains_nrhs = nrhs;
     return HELM_OK;
@@ -724,11 +765,14 @@ struct SoloDev {
     const ChainDev *ch, *md, *sc, *cc;
     int nch, nmd, nsc, ncc, ks_chain, ks_mid, waves, seg_wg, kind, cwaves, crq;
     void *spill, *segws;
+    const ChainDev* mc = nullptr;
+    int nmc = 0;
+    void* mws = nullptr;
 };
 
 static int solo_launch(const sweep_factors_t M, const SoloDev& D, const void* f, void* u, int vec_prec, hipStream_t s) {
     const ProbDev* pd = M->A->pd.as<ProbDev>();
-    IoDev io{f, u, M->fac.p, M->prop.p, M->cmp.p};
+    IoDev io{f, u, M->fac.p, M->prop.p, M->cmp.p, M->msp.p};
     const int B = M->A->B;
     if (D.kind == 2) {
         PhaseScope ph(PH_SWEEP_FRONT, s);
@@ -740,7 +784,9 @@ static int solo_launch(const sweep_factors_t M, const SoloDev& D, const void* f,
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
         bool ok;
-        if (D.kind == 2)
+        if (D.kind == 3)
+            ok = launch_chains_mfma(B, vec_prec, vec_prec, 0, pd, D.mc, D.nmc, nullptr, io, D.mws, nullptr, s);
+        else if (D.kind == 2)
             ok = launch_chains_comp(B, M->cseg, D.crq, vec_prec, vec_prec, 0, pd, D.cc, D.ncc, nullptr, io, D.cwaves,
                                     nullptr, s);
         else if (D.kind == 1)
@@ -762,7 +808,9 @@ static int solo_launch(const sweep_factors_t M, const SoloDev& D, const void* f,
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
         bool ok;
-        if (D.kind == 2)
+        if (D.kind == 3)
+            ok = launch_chains_mfma(B, vec_prec, vec_prec, 1, pd, D.mc, D.nmc, nullptr, io, D.mws, nullptr, s);
+        else if (D.kind == 2)
             ok = launch_chains_comp(B, M->cseg, D.crq, vec_prec, vec_prec, 1, pd, D.cc, D.ncc, nullptr, io, D.cwaves,
                                     nullptr, s);
         else if (D.kind == 1)
@@ -801,7 +849,7 @@ extern "C" int sweep_apply(sweep_factors_t M, const void* f, void* u, int32_t nr
     if ((rc = ensure_solo_chains(M, nrhs, s))) return rc;
     const SoloDev D{M->chains.as<ChainDev>(), M->mids.as<ChainDev>(), M->segch.as<ChainDev>(), M->cchains.as<ChainDev>(),
                     M->nchains, M->nmids, M->nsegch, M->ncch, M->ks_chain, M->ks_mid, M->waves, M->seg_wg, M->kind,
-                    M->cwaves, M->crq, M->spill.p, M->segws.p};
+                    M->cwaves, M->crq, M->spill.p, M->segws.p, M->mchains.as<ChainDev>(), M->nmch, M->mws.p};
     return solo_launch(M, D, f, u, vec_prec, s);
 }
 
@@ -822,7 +870,8 @@ extern "C" int sweep_apply_noalloc(sweep_factors_t M, const void* f, void* u, in
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t o_ch = 0, o_md = o_ch + up(sizeof(ChainDev) * P.ch.size()), o_sc = o_md + up(sizeof(ChainDev) * P.md.size()),
                  o_cc = o_sc + up(sizeof(ChainDev) * P.sc.size()), o_sp = o_cc + up(sizeof(ChainDev) * P.cc.size()),
-                 o_ws = o_sp + up(P.spill_bytes), total = o_ws + up(P.segws_bytes);
+                 o_ws = o_sp + up(P.spill_bytes), o_mc = o_ws + up(P.segws_bytes),
+                 o_mw = o_mc + up(sizeof(ChainDev) * P.mc.size()), total = o_mw + up(P.mws_bytes);
     if (total > (size_t)HELM_NOALLOC_SCRATCH_BYTES)
         return fail(HELM_ENOMEM, "sweep_apply_noalloc: n=%d with %d right-hand sides needs %zu bytes of scratch, the "
                                  "static scratch holds %d", M->A->n, nrhs, total, (int)HELM_NOALLOC_SCRATCH_BYTES);
@@ -834,10 +883,12 @@ extern "C" int sweep_apply_noalloc(sweep_factors_t M, const void* f, void* u, in
         HIPCHK(hipMemcpyAsync(base + o_sc, P.sc.data(), sizeof(ChainDev) * P.sc.size(), hipMemcpyHostToDevice, s));
     if (!P.cc.empty())
         HIPCHK(hipMemcpyAsync(base + o_cc, P.cc.data(), sizeof(ChainDev) * P.cc.size(), hipMemcpyHostToDevice, s));
+    if (!P.mc.empty())
+        HIPCHK(hipMemcpyAsync(base + o_mc, P.mc.data(), sizeof(ChainDev) * P.mc.size(), hipMemcpyHostToDevice, s));
     const SoloDev D{(const ChainDev*)(base + o_ch), (const ChainDev*)(base + o_md), (const ChainDev*)(base + o_sc),
                     (const ChainDev*)(base + o_cc), (int)P.ch.size(), (int)P.md.size(), (int)P.sc.size(),
                     (int)P.cc.size(), P.ks_chain, P.ks_mid, P.waves, P.seg_wg, P.kind, P.cwaves, P.crq, base + o_sp,
-                    base + o_ws};
+                    base + o_ws, (const ChainDev*)(base + o_mc), (int)P.mc.size(), base + o_mw};
     return solo_launch(M, D, f, u, vec_prec, s);
 }
 
@@ -970,7 +1021,7 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
         if (!A[k] || !M[k]) return fail(HELM_EINVAL, "NULL handle at %d", k);
         if (M[k]->A != A[k]) return fail(HELM_EINVAL, "factors %d do not belong to problem %d", k, k);
         if (nrhs[k] < 1) return fail(HELM_EINVAL, "nrhs[%d] must be >= 1", k);
-        if (k > 0 && (A[k]->B != A[0]->B || M[k]->prec != M[0]->prec))
+        if (k > 0 && (A[k]->B != A[0]->B || M[k]->prec != M[0]->prec || M[k]->mfma != M[0]->mfma))
             return fail(HELM_EINVAL, "batch members must share B and factor precision");
         b->A.push_back(A[k]);
         b->M.push_back(M[k]);
@@ -1078,6 +1129,28 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
         if ((rc = build_comp_table(b.get(), crq_env()))) return rc;
     }
     b->kind = pick_kind(b->seg, b->comp);
+    // matrix-core chains (HELM_C64_BF16X3 factors): one wave per (problem, front, 16 right-hand sides),
+    // longest problems first, each with its own workspace
+    b->mfma = M[0]->mfma;
+    if (b->mfma) {
+        std::vector<int> order(count), base(count + 1, 0);
+        for (int p = 0; p < count; ++p) { order[p] = p; base[p + 1] = base[p] + b->nrhs[p]; }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return A[a]->n > A[c]->n; });
+        std::vector<ChainDev> mc;
+        int64_t off = 0;
+        for (int p : order)
+            for (int g = 0; g * 16 < b->nrhs[p]; ++g)
+                for (int f = 0; f < 2; ++f) {
+                    mc.push_back(ChainDev{p, f, g * 16, std::min(16, b->nrhs[p] - g * 16), base[p] + g * 16, 0, off});
+                    off += chainm_ws_f4(A[p]->n, B);
+                }
+        if ((rc = precheck_bytes((double)sizeof(float) * 4 * (double)off, "the matrix-core chains' workspace"))) return rc;
+        if ((rc = b->mws.alloc(sizeof(float) * 4 * (size_t)off))) return rc;
+        if ((rc = b->mch.alloc(sizeof(ChainDev) * mc.size()))) return rc;
+        HIPCHK(hipMemcpy(b->mch.p, mc.data(), sizeof(ChainDev) * mc.size(), hipMemcpyHostToDevice));
+        b->nmch = (int)mc.size();
+        b->kind = 3;
+    }
     // io tables for V_j -> Z_j, and matvec tables Z_j -> W
     std::vector<IoDev> ios((size_t)kk * count);
     std::vector<MvDev> mvz((size_t)kk * count);
@@ -1091,7 +1164,7 @@ extern "C" int helm_batch_create(const helm_problem_t* A, const sweep_factors_t*
             const int64_t blk = (int64_t)b->nrhs[p] * b->N[p];
             ios[(size_t)j * count + p] =
                 IoDev{V + b->voff[p] + j * blk, Z + b->zelem * (b->zoff[p] + j * blk), M[p]->fac.p, M[p]->prop.p,
-                      M[p]->cmp.p};
+                      M[p]->cmp.p, M[p]->msp.p};
             mvz[(size_t)j * count + p] = MvDev{Z + b->zelem * (b->zoff[p] + j * blk), W + b->woff[p], nullptr, b->nrhs[p],
                                                   sys0[p]};
         }
@@ -1148,7 +1221,7 @@ extern "C" int sweep_refactor_batch(helm_batch_t b, void* stream) {
     const int B = b->B;
     HIPCHK(hipMemsetAsync(b->fstatus.p, 0, sizeof(int) * b->count, s));
     {
-        PhaseScope ph(PH_FACTOR, s, 2 + (b->seg ? 1 : 0) + (b->comp ? 1 : 0));
+        PhaseScope ph(PH_FACTOR, s, 2 + (b->seg ? 1 : 0) + (b->comp ? 1 : 0) + (b->mfma ? b->count : 0));
         // middles (few, long) on the side stream, overlapping the many height-B strips
         HIPCHK(hipEventRecord(b->ev_fork, s));
         HIPCHK(hipStreamWaitEvent(b->side, b->ev_fork, 0));
@@ -1170,6 +1243,13 @@ extern "C" int sweep_refactor_batch(helm_batch_t b, void* stream) {
                                  b->ncompw, s))
                 return fail(HELM_EINVAL, "no compression kernel for B=%d", B);
             LAUNCHCHK();
+        }
+        if (b->mfma) {
+            for (int p = 0; p < b->count; ++p) {
+                if (!launch_msplit(B, b->M[p]->fac.p, b->M[p]->msp.p, (int64_t)(b->A[p]->nsub - 1) * b->A[p]->n, s))
+                    return fail(HELM_EINVAL, "no split kernel for B=%d", B);
+                LAUNCHCHK();
+            }
         }
         HIPCHK(hipStreamWaitEvent(s, b->ev_join, 0));
     }
@@ -1217,7 +1297,7 @@ extern "C" int helm_timing_read(double* ms, int64_t* launches, int32_t reset) {
 // device flags (nullptr: all); chains and middles whose systems are all inactive are skipped.
 static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int32_t* active, hipStream_t s) {
     const ProbDev* pd = b->probs.as<ProbDev>();
-    const IoDev none{nullptr, nullptr, nullptr, nullptr, nullptr};
+    const IoDev none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (b->kind == 2) {
         PhaseScope ph(PH_SWEEP_FRONT, s);
         if (!launch_chains_seg(b->B, b->prec, 0, out_prec, 0, pd, b->segch.as<ChainDev>(), b->nsegch, io, none, b->seg_wg,
@@ -1228,7 +1308,9 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int3
     {
         PhaseScope ph(PH_SWEEP_FWD, s);
         bool ok;
-        if (b->kind == 2)
+        if (b->kind == 3)
+            ok = launch_chains_mfma(b->B, 0, out_prec, 0, pd, b->mch.as<ChainDev>(), b->nmch, io, none, b->mws.p, active, s);
+        else if (b->kind == 2)
             ok = launch_chains_comp(b->B, b->cseg, b->crq, 0, out_prec, 0, pd, b->cch.as<ChainDev>(), b->ncch, io, none,
                                     b->cwaves, active, s);
         else if (b->kind == 1)
@@ -1250,7 +1332,9 @@ static int batch_sweep(helm_batch_t b, const IoDev* io, int out_prec, const int3
     {
         PhaseScope ph(PH_SWEEP_BWD, s);
         bool ok;
-        if (b->kind == 2)
+        if (b->kind == 3)
+            ok = launch_chains_mfma(b->B, 0, out_prec, 1, pd, b->mch.as<ChainDev>(), b->nmch, io, none, b->mws.p, active, s);
+        else if (b->kind == 2)
             ok = launch_chains_comp(b->B, b->cseg, b->crq, 0, out_prec, 1, pd, b->cch.as<ChainDev>(), b->ncch, io, none,
                                     b->cwaves, active, s);
         else if (b->kind == 1)
@@ -1305,6 +1389,20 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
         *per = (double)t / reps;
         return HELM_OK;
     };
+    if (b->mfma) {
+        // HELM_C64_BF16X3 factors: the matrix-core chains are the schedule; time them
+        b->kind = 3;
+        double per = 0;
+        rc = time_one(&per);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+        if (ksplit) *ksplit = 16;
+        if (waves) *waves = 1;
+        if (segmented) *segmented = 3;
+        if (ms) *ms = per;
+        return HELM_OK;
+    }
     if (b->seg) {
         // segmented chains with workgroups of the fewest waves that hold one right-hand side of the
         // largest problem, and of 2x and 4x as many (several right-hand sides per workgroup) where they fit
@@ -1366,7 +1464,7 @@ extern "C" int sweep_apply_batch(helm_batch_t b, const void* const* f, void* con
     std::vector<IoDev> io(b->count);
     for (int p = 0; p < b->count; ++p) {
         if (!f[p] || !u[p]) return fail(HELM_EINVAL, "NULL vector for problem %d", p);
-        io[p] = IoDev{f[p], u[p], b->M[p]->fac.p, b->M[p]->prop.p, b->M[p]->cmp.p};
+        io[p] = IoDev{f[p], u[p], b->M[p]->fac.p, b->M[p]->prop.p, b->M[p]->cmp.p, b->M[p]->msp.p};
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemcpy(b->io_apply.p, io.data(), sizeof(IoDev) * b->count, hipMemcpyHostToDevice));

@@ -158,6 +158,7 @@ struct IoDev {
     const void* fac;    // factor store of the problem (complex elements of the factor precision)
     const void* prop;   // segment propagators of the problem's front strips (segmented sweep), or nullptr
     const void* cmp;    // compressed blocks of the problem's moving strips (compressed chains), or nullptr
+    const void* msp;    // split (bf16 hi / lo) copy of the F / E / moving strips' blocks (matrix-core chains), or nullptr
 };
 
 // Columns per segment of the segmented strip solves.

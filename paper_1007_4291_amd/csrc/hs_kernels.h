@@ -190,6 +190,17 @@ bool launch_chains_comp(int B, int seg, int rq, int in_prec, int out_prec, int p
                         const int32_t* active, hipStream_t s);
 size_t chainc_lds_bytes(int B, int seg, int rq, int waves);
 
+// Matrix-core chains (factor precision HELM_C64_BF16X3): one wave per chain (problem, front, up to 16
+// right-hand sides), every strip of the front in the phase's order, block products in bf16x3 on
+// v_mfma_f32_16x16x32_bf16.  io[p].msp holds problem p's split blocks (launch_msplit), ws a workspace
+// of chainm_ws_f4(n, B) float4 per chain at chain.spill_off.  Returns false for unsupported B.
+bool chainm_supported(int B);
+int64_t chainm_ws_f4(int n, int B);
+// Split copy of ncols stored columns (complex64 factors, B-row strips) into msp (same layout).
+bool launch_msplit(int B, const void* fac, void* msp, int64_t ncols, hipStream_t s);
+bool launch_chains_mfma(int B, int in_prec, int out_prec, int phase, const ProbDev* probs, const ChainDev* chains,
+                        int nchains, const IoDev* io, IoDev io_val, void* ws, const int32_t* active, hipStream_t s);
+
 // Device address of the allocation-free entry point's static scratch array on the current device
 // (looked up once per device), or nullptr with noalloc_error() set.
 void* noalloc_scratch();

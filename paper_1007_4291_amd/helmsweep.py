@@ -23,6 +23,7 @@ HELM_EHIP = -3
 HELM_ESINGULAR = -4
 HELM_C128 = 0
 HELM_C64 = 1
+HELM_C64_BF16X3 = 2      # complex64 factors, block products on the matrix cores in bf16x3 (sweep_factor only)
 
 # every symbol the header declares
 EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_reassemble", "helm_problem_n", "helm_matvec",

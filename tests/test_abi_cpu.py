@@ -75,3 +75,14 @@ def test_null_handles_rejected(hs):
     L.helm_free(None)
     L.sweep_free(None)
     L.helm_batch_free(None)
+
+
+def test_header_constants_match_binding():
+    """Every HELM_* integer constant of include/helmsweep.h has the same value in the binding."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "helmsweep.h")).read()
+    found = dict((k, int(v)) for k, v in re.findall(r"#define (HELM_[A-Z0-9_]+) \(?(-?\d+)\)?\s", hdr))
+    assert {"HELM_C128", "HELM_C64", "HELM_C64_BF16X3", "HELM_EINVAL"} <= set(found)
+    for k, v in found.items():
+        if hasattr(hs, k):
+            assert getattr(hs, k) == v, k
