@@ -133,8 +133,17 @@ __global__ __launch_bounds__(64) void k_chainM(const ProbDev* __restrict__ probs
             is2m[m][q] = r < BS ? ccast<float, double>(is2) : make_float2(0.f, 0.f);
         }
 
-    // W = Lambda^{-1} Z for this wave's 16 right-hand sides; cs: the column's split packed block
-    auto product = [&](const HS_GLOBAL hs_u2* cs, const float2 (&z)[MT][4], float2 (&w)[MT][4]) __attribute__((always_inline)) {
+    // Operands of one column, requested one column ahead of their use: this lane's split entries of
+    // Lambda_t^{-1}, the column coupling E_t, the layer coupling and layer-row values of the input
+    // (forward pass of a layer strip), the stored forward product and old output (backward pass).
+    struct Col {
+        hs_u2 a[MT][MT][4];
+        float2 e, cpl, y;
+        double2 fv;
+        f32x4_t wsv[MS::WSV];
+    };
+    // W = Lambda^{-1} Z for this wave's 16 right-hand sides from the column's split entries
+    auto product = [&](const Col& C, const float2 (&z)[MT][4], float2 (&w)[MT][4]) __attribute__((always_inline)) {
         u32x4_t bh[MT], bl[MT];
 #pragma unroll
         for (int s = 0; s < MT; ++s)
@@ -154,20 +163,18 @@ __global__ __launch_bounds__(64) void k_chainM(const ProbDev* __restrict__ probs
                 u32x4_t arh, arl, aih, ail;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int o = aoff[m][s][q];
-                    hs_u2 v = cs[o >= 0 ? o : 0];
-                    if (o < 0) v = hs_u2{0u, 0u};
-                    arh[q] = v.x ^ 0x80000000u;                     // (Lr_hi, -Li_hi)
-                    arl[q] = v.y ^ 0x80000000u;                     // (Lr_lo, -Li_lo)
+                    const hs_u2 v = C.a[m][s][q];
+                    arh[q] = v.x ^ 0x80000000u;                         // (Lr_hi, -Li_hi)
+                    arl[q] = v.y ^ 0x80000000u;                         // (Lr_lo, -Li_lo)
                     aih[q] = __builtin_amdgcn_alignbit(v.x, v.x, 16);   // (Li_hi, Lr_hi)
                     ail[q] = __builtin_amdgcn_alignbit(v.y, v.y, 16);   // (Li_lo, Lr_lo)
                 }
                 const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, bh[s]), Bl = __builtin_bit_cast(bf16x8_t, bl[s]);
                 ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, arl), Bh, ar, 0, 0, 0);
-                ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, arh), Bl, ar, 0, 0, 0);
-                ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, arh), Bh, ar, 0, 0, 0);
                 ai = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ail), Bh, ai, 0, 0, 0);
+                ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, arh), Bl, ar, 0, 0, 0);
                 ai = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, aih), Bl, ai, 0, 0, 0);
+                ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, arh), Bh, ar, 0, 0, 0);
                 ai = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, aih), Bh, ai, 0, 0, 0);
             }
 #pragma unroll
@@ -189,6 +196,44 @@ __global__ __launch_bounds__(64) void k_chainM(const ProbDev* __restrict__ probs
             for (int q = 0; q < 4; ++q) is2[m][q] = full ? is2f[m][q] : is2m[m][q];
         // physical row (1-based) of local row r of a full strip
         auto full_row = [&](int r) { return jl - dirF * (BS - 1 - r); };
+        // the layer-row input / output of this lane (slot lanes of live right-hand sides)
+        const bool io_slot = qok && g == SG && !(MODE == MODE_FWD && full);
+        const int64_t yin_row = MODE == MODE_FWD ? jl - dirF - 1 : jl + dirF - 1;
+
+        // requests of column t (0 <= t < n) for the forward (fw) or backward pass
+        auto fetch = [&](int t, bool fw, Col& C) __attribute__((always_inline)) {
+            const int col = cd > 0 ? t : n - 1 - t;
+            const HS_GLOBAL hs_u2* const cs = msp + (int64_t)t * STRIDE;
+            const HS_GLOBAL float2* const cc = fac + (int64_t)t * STRIDE;
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int s = 0; s < MT; ++s)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int o = aoff[m][s][q];
+                        C.a[m][s][q] = cs[o >= 0 ? o : 0];
+                    }
+            C.e = gld(cc + PACK + XCOL_E);
+            if (fw) {
+                C.cpl = gld(cc + PACK + (MODE == MODE_FWD ? XCOL_APREV : XCOL_ANEXT));
+                C.y = ccast<float, double>(ld2(uout + (io_slot ? yin_row * n + col : (int64_t)0)));
+                if (MODE == MODE_FWD) C.fv = ld2(fin + (io_slot ? (int64_t)(jl - 1) * n + col : (int64_t)0));
+            } else {
+#pragma unroll
+                for (int c = 0; c < MS::WSV; ++c) C.wsv[c] = ws[((int64_t)t * MS::WSV + c) * 64];
+                if (MODE == MODE_BWD) C.y = ccast<float, double>(ld2(uout + (io_slot ? (int64_t)(jl - 1) * n + col : (int64_t)0)));
+            }
+        };
+        auto zero_outside = [&](Col& C) __attribute__((always_inline)) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int s = 0; s < MT; ++s)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (aoff[m][s][q] < 0) C.a[m][s][q] = hs_u2{0u, 0u};
+        };
 
         // ---- forward pass
         float2 w[MT][4];
@@ -197,44 +242,45 @@ __global__ __launch_bounds__(64) void k_chainM(const ProbDev* __restrict__ probs
 #pragma unroll
             for (int q = 0; q < 4; ++q) w[m][q] = make_float2(0.f, 0.f);
         float2 eprev = make_float2(0.f, 0.f);                // E of the previous column (none at t = 0)
-        for (int t = 0; t < n; ++t) {
+        auto fstep = [&](int t, Col& C, Col& Nx) __attribute__((always_inline)) {
+            if (t + 1 < n) fetch(t + 1, true, Nx);
+            zero_outside(C);
             const int col = cd > 0 ? t : n - 1 - t;
-            const HS_GLOBAL float2* const cc = fac + (int64_t)t * STRIDE;
             float2 z[MT][4];
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) z[m][q] = cmul<float>(cscale<float>(cmul<float>(eprev, is2[m][q]), -1.f), w[m][q]);
-            if (qok) {
-                if (MODE == MODE_FWD && full) {
+            if (qok && MODE == MODE_FWD && full) {
 #pragma unroll
-                    for (int m = 0; m < MT; ++m)
+                for (int m = 0; m < MT; ++m)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int r = 16 * m + 4 * g + q;
-                            if (r < BS) z[m][q] = cadd<float>(z[m][q], ccast<float, double>(ld2(fin + (int64_t)(full_row(r) - 1) * n + col)));
-                        }
-                } else if (g == SG) {
-                    float2 gv;
-                    if (MODE == MODE_FWD) {
-                        const float2 yp = ccast<float, double>(ld2(uout + (int64_t)(jl - dirF - 1) * n + col));
-                        gv = csub<float>(ccast<float, double>(ld2(fin + (int64_t)(jl - 1) * n + col)),
-                                         cmul<float>(gld(cc + PACK + XCOL_APREV), yp));
-                    } else {
-                        const float2 yn = ccast<float, double>(ld2(uout + (int64_t)(jl + dirF - 1) * n + col));
-                        gv = cmul<float>(gld(cc + PACK + XCOL_ANEXT), yn);
+                    for (int q = 0; q < 4; ++q) {
+                        const int r = 16 * m + 4 * g + q;
+                        if (r < BS) z[m][q] = cadd<float>(z[m][q], ccast<float, double>(ld2(fin + (int64_t)(full_row(r) - 1) * n + col)));
                     }
-                    z[SMT][SQ] = cadd<float>(z[SMT][SQ], gv);
-                }
+            } else if (io_slot) {
+                const float2 gv = MODE == MODE_FWD
+                                      ? csub<float>(make_float2((float)C.fv.x, (float)C.fv.y), cmul<float>(C.cpl, C.y))
+                                      : cmul<float>(C.cpl, C.y);
+                z[SMT][SQ] = cadd<float>(z[SMT][SQ], gv);
             }
-            product(msp + (int64_t)t * STRIDE, z, w);
+            product(C, z, w);
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
                     ws[((int64_t)t * MS::WSV + 2 * m + c) * 64] =
                         f32x4_t{w[m][2 * c].x, w[m][2 * c].y, w[m][2 * c + 1].x, w[m][2 * c + 1].y};
-            eprev = gld(cc + PACK + XCOL_E);
+            eprev = C.e;
+        };
+        {
+            Col C0, C1;
+            fetch(0, true, C0);
+            for (int t = 0; t < n; t += 2) {                 // two columns per pass: the buffers swap roles
+                fstep(t, C0, C1);
+                if (t + 1 < n) fstep(t + 1, C1, C0);
+            }
         }
 
         // ---- backward pass and the strip's output
@@ -243,46 +289,57 @@ __global__ __launch_bounds__(64) void k_chainM(const ProbDev* __restrict__ probs
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int q = 0; q < 4; ++q) x[m][q] = w[m][q];
-        for (int t = n - 1; t >= 0; --t) {
+        auto output = [&](int t, float2 yold) __attribute__((always_inline)) {
             const int col = cd > 0 ? t : n - 1 - t;
-            if (t < n - 1) {
-                const HS_GLOBAL float2* const cc = fac + (int64_t)t * STRIDE;
-                const float2 e = gld(cc + PACK + XCOL_E);
-                float2 v[MT][4], p[MT][4];
+            if (qok && full) {
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) v[m][q] = cmul<float>(is2[m][q], x[m][q]);
-                product(msp + (int64_t)t * STRIDE, v, p);
-#pragma unroll
-                for (int m = 0; m < MT; ++m)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const f32x4_t wv = ws[((int64_t)t * MS::WSV + 2 * m + c) * 64];
-                        x[m][2 * c] = csub<float>(make_float2(wv[0], wv[1]), cmul<float>(e, p[m][2 * c]));
-                        x[m][2 * c + 1] = csub<float>(make_float2(wv[2], wv[3]), cmul<float>(e, p[m][2 * c + 1]));
-                    }
-            }
-            if (qok) {
-                if (full) {
-#pragma unroll
-                    for (int m = 0; m < MT; ++m)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int r = 16 * m + 4 * g + q;
-                            if (r < BS) {
-                                HS_GLOBAL TO* const dst = uout + (int64_t)(full_row(r) - 1) * n + col;
-                                float2 y = x[m][q];
-                                if (MODE == MODE_BWD) y = csub<float>(ccast<float, double>(ld2(dst)), y);
-                                gst(dst, cvt_out<TO, float>(y));
-                            }
+                    for (int q = 0; q < 4; ++q) {
+                        const int r = 16 * m + 4 * g + q;
+                        if (r < BS) {
+                            HS_GLOBAL TO* const dst = uout + (int64_t)(full_row(r) - 1) * n + col;
+                            float2 y = x[m][q];
+                            if (MODE == MODE_BWD) y = csub<float>(ccast<float, double>(ld2(dst)), y);
+                            gst(dst, cvt_out<TO, float>(y));
                         }
-                } else if (g == SG) {
-                    HS_GLOBAL TO* const dst = uout + (int64_t)(jl - 1) * n + col;
-                    float2 y = x[SMT][SQ];
-                    if (MODE == MODE_BWD) y = csub<float>(ccast<float, double>(ld2(dst)), y);
-                    gst(dst, cvt_out<TO, float>(y));
+                    }
+            } else if (io_slot) {
+                float2 y = x[SMT][SQ];
+                if (MODE == MODE_BWD) y = csub<float>(yold, y);
+                gst(uout + (int64_t)(jl - 1) * n + col, cvt_out<TO, float>(y));
+            }
+        };
+        auto bstep = [&](int t, Col& C, Col& Nx) __attribute__((always_inline)) {
+            if (t >= 1) fetch(t - 1, false, Nx);
+            zero_outside(C);
+            float2 v[MT][4], p[MT][4];
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[m][q] = cmul<float>(is2[m][q], x[m][q]);
+            product(C, v, p);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const f32x4_t wv = C.wsv[2 * m + c];
+                    x[m][2 * c] = csub<float>(make_float2(wv[0], wv[1]), cmul<float>(C.e, p[m][2 * c]));
+                    x[m][2 * c + 1] = csub<float>(make_float2(wv[2], wv[3]), cmul<float>(C.e, p[m][2 * c + 1]));
                 }
+            output(t, C.y);
+        };
+        {
+            Col C0, C1;
+            // column n-1: x = w, its old output value
+            float2 ylast = make_float2(0.f, 0.f);
+            if (MODE == MODE_BWD && io_slot)
+                ylast = ccast<float, double>(ld2(uout + (int64_t)(jl - 1) * n + (cd > 0 ? n - 1 : 0)));
+            if (n >= 2) fetch(n - 2, false, C0);
+            output(n - 1, ylast);
+            for (int t = n - 2; t >= 0; t -= 2) {            // two columns per pass: the buffers swap roles
+                bstep(t, C0, C1);
+                if (t - 1 >= 0) bstep(t - 1, C1, C0);
             }
         }
     }
