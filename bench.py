@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0          # MI355X dense bf16 matrix peak
 
 
 def parse():
@@ -34,8 +35,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched", choices=["batched", "lens255", "grf1023", "const63"])
-    ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "lens255", "grf1023", "const63", "waveguide2047"])
+    ap.add_argument("--prec", default="c64", choices=["c64", "c128", "bf16x3"],
+                    help="factor precision and sweep arithmetic (bf16x3: the matrix-core block products)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 comparison (0: skip)")
     ap.add_argument("--graph-steps", type=int, default=1,
                     help="timed steps with each restart cycle replayed as a captured hipGraph (0: skip)")
@@ -57,6 +59,10 @@ def build_workload(name: str, per_size: int):
     elif name == "grf1023":
         probs = [W.cfg3()]
         desc = "n=1023, omega/2pi=128, Gaussian random velocity, Gaussian source, widths 12, FGMRES(20) to 1e-6"
+    elif name == "waveguide2047":
+        probs = [W.cfg5()]
+        desc = ("n=2047, omega/2pi=256, waveguide velocity, 64 point sources on row 205, widths 16 (B=17), "
+                "FGMRES(30) to 1e-6")
     else:
         probs = [W.cfg1()]
         desc = "n=63, omega/2pi=8, c=1, point source, widths 8, FGMRES(20) to 1e-6"
@@ -128,6 +134,22 @@ def copy_bandwidth(torch, gib=2):
     del a, b
     torch.cuda.empty_cache()
     return nbytes / best / 1e9
+
+
+def mfma_flops(probs, B):
+    """Flops the matrix-core chains' instructions execute in one launch (one phase): per strip and
+    column (both passes, 2n - 1 block products), per wave of 16 right-hand sides, 6 v_mfma_f32_16x16x32_bf16
+    (three bf16 products each of the real and imaginary output) per pair of 16-row tile and 32-wide K
+    step, 16 x 16 x 32 x 2 flops each -- padding of the B rows to 16-row tiles included."""
+    mt = (B + 15) // 16
+    fl = 0
+    for p in probs:
+        n = p.n
+        c = (n + 1) // 2 if n % 2 else n // 2 + 1
+        strips = (c - 1 - B) + (n - B - c) + 2
+        waves = -(-p.nrhs // 16)
+        fl += waves * strips * (2 * n - 1) * 6 * mt * mt * 16 * 16 * 32 * 2
+    return fl
 
 
 def sweep_bytes_flops(probs, B, fac_bytes, moving_only):
@@ -298,7 +320,7 @@ def main():
     import paper_1007_4291_amd.helmsweep as hs
 
     probs, desc = build_workload(a.workload, a.per_size)
-    prec = hs.HELM_C64 if a.prec == "c64" else hs.HELM_C128
+    prec = {"c64": hs.HELM_C64, "c128": hs.HELM_C128, "bf16x3": hs.HELM_C64_BF16X3}[a.prec]
     B = probs[0].mpml_w + 1
     tot_unknowns = sum(p.nrhs * p.N for p in probs)
     nsys = sum(p.nrhs for p in probs)
@@ -319,31 +341,48 @@ def main():
 
     # roofline of the dominant kernel: the sweep chain kernel (forward + backward launches); with the
     # compressed chains the moving layers' kernel, timed apart from the front strips' launches
-    fac_b = 8 if prec == hs.HELM_C64 else 16
+    fac_b = 16 if prec == hs.HELM_C128 else 8
     skind = schedule.get("kind", 1 if schedule.get("segmented") else 0)
     bytes_per_launch, fl = sweep_bytes_flops(probs, B, fac_b, moving_only=(skind == 2))
     ms_f, n_f = ph["sweep_fwd"]
     ms_b, n_b = ph["sweep_bwd"]
     avg_ms = (ms_f + ms_b) / max(1, n_f + n_b)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    kind = {0: "plain", 1: f"segmented-{schedule.get('waves')}w", 2: f"compressed-{schedule.get('ksplit')}rq"}[skind]
+    kind = {0: "plain", 1: f"segmented-{schedule.get('waves')}w", 2: f"compressed-{schedule.get('ksplit')}rq",
+            3: "matrix-core"}[skind]
     traffic = measured_traffic(a.workload, a.prec, kind)
     kname = {0: f"k_sweep{'2' if schedule.get('waves') == 2 else ''} (chains)",
              1: f"k_sweepP (segmented chains, {schedule.get('waves')}-wave workgroups)",
              2: f"k_chainC (compressed moving-layer chains, {schedule.get('ksplit')} right-hand sides and "
-                f"{schedule.get('waves')} waves per workgroup)"}[skind] + " forward/backward launches"
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": int(traffic) if traffic else None,
-            "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
-            "launches": n_f + n_b, "algorithmic_bytes_per_launch": int(bytes_per_launch),
-            "front_strips_ms_per_step": round(ph["sweep_front"][0] / a.steps, 3),
-            "tflops": round(fl / (avg_ms * 1e-3) / 1e12, 4)}
-    roof["frac_fp32_vector"] = round(roof["tflops"] / 157.3, 5)      # of the 157.3 TFLOP/s FP32 vector peak
-    roof["bytes_formula"] = ("per launch: sum over problems of (strips solved) x 2 passes x n x B(B+1)/2 x "
-                             f"{fac_b} B + N x R x {fac_b} B")
-    hbm_meas = copy_bandwidth(torch)
-    roof["measured_copy_gbs"] = round(hbm_meas, 1)
-    roof["frac_of_measured_copy"] = round(achieved / hbm_meas, 5)
+                f"{schedule.get('waves')} waves per workgroup)",
+             3: "k_chainM (matrix-core chains, bf16x3 on v_mfma_f32_16x16x32_bf16, 16 right-hand sides per wave)"}[skind] \
+        + " forward/backward launches"
+    if skind == 3:
+        # the matrix-core chains: MFMA work (3 bf16 products per real product) against the dense bf16 peak
+        mf = mfma_flops(probs, B)
+        ach = mf / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 4), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / MFMA_BF16_PEAK_TFLOPS, 6), "traffic": None, "kernel": kname,
+                "avg_launch_ms": round(avg_ms, 4), "launches": n_f + n_b, "mfma_flops_per_launch": int(mf),
+                "algorithmic_complex_flops_per_launch": int(fl),
+                "hbm_gbs_algorithmic": round(achieved, 2)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": int(traffic) if traffic else None,
+                "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
+                "launches": n_f + n_b, "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                "front_strips_ms_per_step": round(ph["sweep_front"][0] / a.steps, 3),
+                "tflops": round(fl / (avg_ms * 1e-3) / 1e12, 4)}
+    if skind != 3:
+        roof["frac_fp32_vector"] = round(roof["tflops"] / 157.3, 5)      # of the 157.3 TFLOP/s FP32 vector peak
+        roof["bytes_formula"] = ("per launch: sum over problems of (strips solved) x 2 passes x n x B(B+1)/2 x "
+                                 f"{fac_b} B + N x R x {fac_b} B")
+        hbm_meas = copy_bandwidth(torch)
+        roof["measured_copy_gbs"] = round(hbm_meas, 1)
+        roof["frac_of_measured_copy"] = round(achieved / hbm_meas, 5)
+    else:
+        roof["flops_formula"] = ("per launch: sum over chains (problem, front, 16 right-hand sides) of strips x "
+                                 "(2n - 1) columns x 6 MFMA x (16-row tiles)^2 x 16 x 16 x 32 x 2")
 
     out = {"metric": "preconditioned solves/sec (RHS*N unknowns/s) at 1e-6 residual; FP32-batched vs FP64",
            "value": value, "unit": "RHS*N unknowns/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -371,23 +410,39 @@ def main():
                         "equals_eager": same}
         print(f"[bench] graph form: {tg * 1e3:.1f} ms/step (equal to eager: {same})", file=sys.stderr, flush=True)
 
+    def other_leg(key, p2, name):
+        """The same steps with another factor precision: its rate and the largest relative difference of
+        its solutions from the main run's."""
+        r2 = Runner(hs, torch, probs, p2)
+        sch2 = r2.batch.tune(reps=1)
+        t2, _ = timed(r2, torch, a.fp64_steps, 1 if a.warmup > 0 else 0)
+        err = max(float(torch.linalg.vector_norm(u1 - u2) / torch.linalg.vector_norm(u2)) for u1, u2 in zip(u_main, r2.u))
+        out[key] = {"value": tot_unknowns / t2, "ms_per_step": t2 * 1e3, "iters_max": max(r2.last.iters),
+                    "sweep_schedule": sch2, "max_rel_diff_of_solutions": err}
+        print(f"[bench] {name}: {t2 * 1e3:.1f} ms/step; ratio {t2 / t_step:.2f}x; diff {err:.2e}", file=sys.stderr,
+              flush=True)
+        del r2
+        torch.cuda.empty_cache()
+        return t2, err
+
     if a.fp64_steps > 0 and prec != hs.HELM_C128:
         del run
         torch.cuda.empty_cache()
-        run64 = Runner(hs, torch, probs, hs.HELM_C128)
-        schedule64 = run64.batch.tune(reps=1)
-        t64, _ = timed(run64, torch, a.fp64_steps, 1)
-        err = max(float(torch.linalg.vector_norm(u1 - u2) / torch.linalg.vector_norm(u2))
-                  for u1, u2 in zip(u_main, run64.u))
-        out["fp64"] = {"value": tot_unknowns / t64, "ms_per_step": t64 * 1e3,
-                       "iters_max": max(run64.last.iters), "sweep_schedule": schedule64}
-        out["speedup_vs_fp64"] = t64 / t_step
-        out["max_rel_err_vs_fp64_gpu"] = err
-        print(f"[bench] c128: {t64 * 1e3:.1f} ms/step; speedup {t64 / t_step:.2f}x; err {err:.2e}",
-              file=sys.stderr, flush=True)
-        del run64
+        if prec == hs.HELM_C64_BF16X3:
+            other_leg("c64_vector", hs.HELM_C64, "c64 (FP32 vector sweep)")
+        try:
+            t64, err = other_leg("fp64", hs.HELM_C128, "c128")
+            out["speedup_vs_fp64"] = t64 / t_step
+            out["max_rel_err_vs_fp64_gpu"] = err
+        except RuntimeError as e:        # e.g. the FP64 Krylov basis and factors exceed the device memory
+            out["fp64"] = {"skipped": str(e)[:300]}
+            print(f"[bench] c128 leg skipped: {e}", file=sys.stderr, flush=True)
 
-    if not a.no_cpu_baseline:
+    if a.workload == "waveguide2047":
+        out["cpu_baseline"] = {"value": None, "kind": "oracle", "skipped": (
+            "one system of this workload takes the oracle several minutes (about 2000 strip factorisations and "
+            "15 FGMRES iterations of 2000 banded strip solves each), beyond the bounded sample this line allows")}
+    elif not a.no_cpu_baseline:
         cb, sols = cpu_baseline(a.workload, a.per_size)
         out["cpu_baseline"] = cb
         errs = []
