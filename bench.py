@@ -43,6 +43,10 @@ def parse():
                     help="timed steps with each restart cycle replayed as a captured hipGraph (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-size", type=int, default=32, help="problems per size in the batched workload")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1007_4291_amd", "schedules.json"),
+                    help="JSON cache of tuned sweep schedules (keyed by problem sizes, RHS counts, widths, "
+                         "precision); a cached schedule is applied without timing")
+    ap.add_argument("--retune", action="store_true", help="time the schedule candidates even when cached")
     return ap.parse_args()
 
 
@@ -328,7 +332,7 @@ def main():
           file=sys.stderr, flush=True)
 
     run = Runner(hs, torch, probs, prec)
-    schedule = run.batch.tune(reps=2)        # autotuned sweep schedule (setup, not timed)
+    schedule = run.batch.tune(reps=2, cache=a.tune_cache, retune=a.retune)   # autotuned schedule (setup, not timed)
     print(f"[bench] schedule {schedule}", file=sys.stderr, flush=True)
     t_step, ph = timed(run, torch, a.steps, a.warmup)
     res = run.last
@@ -414,7 +418,7 @@ def main():
         """The same steps with another factor precision: its rate and the largest relative difference of
         its solutions from the main run's."""
         r2 = Runner(hs, torch, probs, p2)
-        sch2 = r2.batch.tune(reps=1)
+        sch2 = r2.batch.tune(reps=1, cache=a.tune_cache, retune=a.retune)
         t2, _ = timed(r2, torch, a.fp64_steps, 1 if a.warmup > 0 else 0)
         err = max(float(torch.linalg.vector_norm(u1 - u2) / torch.linalg.vector_norm(u2)) for u1, u2 in zip(u_main, r2.u))
         out[key] = {"value": tot_unknowns / t2, "ms_per_step": t2 * 1e3, "iters_max": max(r2.last.iters),

@@ -222,6 +222,15 @@ int sweep_apply_batch(helm_batch_t b, const void* const* f, void* const* u, void
 int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32_t* ksplit, int32_t* waves,
                     int32_t* segmented, double* ms);
 
+/* a7 -- Apply a sweep schedule found earlier by helm_batch_tune (on a batch of the same problem sizes,
+ * right-hand-side counts, strip height and factor precision), without timing anything: kind, ksplit
+ * and waves as helm_batch_tune reports them (kind 0 plain chains: ksplit divides the right-hand-side
+ * lanes of a wave, waves 1 or 2; kind 1 segmented chains: waves = their workgroup size; kind 2
+ * compressed moving chains: ksplit = 4 or 8 right-hand sides per workgroup; kind 3 matrix-core chains,
+ * for HELM_C64_BF16X3 factors).  Returns HELM_EINVAL if the batch cannot run that schedule (and keeps
+ * its current one).  Host-side tables only; synchronous. */
+int helm_batch_set_schedule(helm_batch_t b, int32_t kind, int32_t ksplit, int32_t waves);
+
 /* a2 for the whole batch (Algorithm 3 for every problem): recompute the factors of every member
  * from its problem's current tables, all height-B strips of all problems in one launch and the
  * middle strips in a second one that overlaps it, then (segmented sweep) the segment propagators of

@@ -1458,6 +1458,41 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
     return HELM_OK;
 }
 
+extern "C" int helm_batch_set_schedule(helm_batch_t b, int32_t kind, int32_t ksplit, int32_t waves) {
+    if (!b) return fail(HELM_EINVAL, "NULL argument");
+    const int q = chain_rhs_per_wave(b->B);
+    int rc = HELM_OK;
+    switch (kind) {
+        case 0:
+            if (ksplit < 1 || ksplit > q || q % ksplit || waves < 1 || waves > (b->B <= 17 ? 2 : 1))
+                return fail(HELM_EINVAL, "plain chains: ksplit %d / waves %d not available for B=%d", ksplit, waves, b->B);
+            if ((rc = build_chain_tables(b, ksplit, b->ks_mid))) return rc;
+            b->waves = waves;
+            break;
+        case 1:
+            if (!b->seg) return fail(HELM_EINVAL, "segmented chains not available for this batch");
+            if (!seg_fits(b->prec == HELM_C128 ? 0 : 1, b->B, waves, b->seg_maxn))
+                return fail(HELM_EINVAL, "segmented chains: %d waves per workgroup do not fit", waves);
+            if ((rc = build_seg_table(b, waves))) return rc;
+            break;
+        case 2:
+            if (!b->comp) return fail(HELM_EINVAL, "compressed chains not available for this batch");
+            if (ksplit != 4 && ksplit != 8) return fail(HELM_EINVAL, "compressed chains: ksplit must be 4 or 8");
+            if ((rc = build_seg_table(b, 0))) return rc;
+            if ((rc = build_comp_table(b, ksplit))) return rc;
+            if (b->crq != ksplit) return fail(HELM_EINVAL, "compressed chains: %d right-hand sides do not fit", ksplit);
+            break;
+        case 3:
+            if (!b->mfma) return fail(HELM_EINVAL, "matrix-core chains need HELM_C64_BF16X3 factors");
+            b->drop_graph();
+            break;
+        default:
+            return fail(HELM_EINVAL, "unknown schedule kind %d", kind);
+    }
+    b->kind = kind;
+    return HELM_OK;
+}
+
 extern "C" int sweep_apply_batch(helm_batch_t b, const void* const* f, void* const* u, void* stream) {
     if (!b || !f || !u) return fail(HELM_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;

@@ -28,7 +28,7 @@ HELM_C64_BF16X3 = 2      # complex64 factors, block products on the matrix cores
 # every symbol the header declares
 EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_reassemble", "helm_problem_n", "helm_matvec",
            "sweep_factor", "sweep_refactor", "sweep_factor_bytes", "sweep_apply", "sweep_apply_noalloc", "sweep_subsolve", "sweep_num_subproblems", "sweep_subproblem_rows",
-           "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "sweep_refactor_batch", "helm_batch_tune",
+           "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "sweep_refactor_batch", "helm_batch_tune", "helm_batch_set_schedule",
            "helm_batch_set_graph", "helm_free", "sweep_free",
            "helm_batch_free", "helm_timing_enable", "helm_timing_read"]
 PHASES = ["assemble", "factor", "sweep_fwd", "sweep_mid", "sweep_bwd", "matvec", "krylov", "sweep_front"]
@@ -74,6 +74,7 @@ def _load() -> C.CDLL:
         "helm_batch_tune": (C.c_int, [vp, C.c_int32, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "helm_batch_set_graph": (C.c_int, [vp, C.c_int32]),
+        "helm_batch_set_schedule": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32]),
         "helm_free": (None, [vp]),
         "sweep_free": (None, [vp]),
         "helm_batch_free": (None, [vp]),
@@ -360,18 +361,61 @@ class Batch:
         """Run each FGMRES restart cycle of later solves as one replay of a captured hipGraph (a7)."""
         _check(_lib.helm_batch_set_graph(self._h, 1 if on else 0))
 
-    def tune(self, reps: int = 2, stream=None) -> dict:
+    def schedule_key(self) -> str:
+        """Key of this batch's schedule in a tuning cache: strip height, factor precision and the
+        multiset of (n, right-hand sides) of its members."""
+        sizes = sorted((a.n, int(r)) for a, r in zip(self.problems, self.nrhs))
+        runs = []
+        for nr in sizes:
+            if runs and runs[-1][0] == nr:
+                runs[-1][1] += 1
+            else:
+                runs.append([nr, 1])
+        p0 = self.problems[0].params
+        return (f"w={p0.mpml_w};pml={p0.pml_w};bc={p0.b_convention};prec={self.factors[0].prec};"
+                + ",".join(f"{c}x(n={n},R={r})" for (n, r), c in runs))
+
+    def set_schedule(self, sched: dict):
+        """Use a schedule found earlier by tune() (kind, ksplit, waves) without timing anything."""
+        _check(_lib.helm_batch_set_schedule(self._h, int(sched["kind"]), int(sched["ksplit"]), int(sched["waves"])))
+
+    def tune(self, reps: int = 2, stream=None, cache: Optional[str] = None, retune: bool = False) -> dict:
         """Pick the fastest sweep schedule for this batch by timing every candidate (a7 autotuner).
 
         Overwrites the batch's Krylov work space.  Returns {"kind", "segmented", "ksplit", "waves",
         "ms_per_apply"}: kind 0 plain chains (ksplit = the split, waves per chain), 1 segmented chains
         (waves = their workgroup size, ksplit 0), 2 compressed moving chains (ksplit = right-hand sides per
-        workgroup, waves = its waves); segmented = 1 for kinds 1 and 2."""
+        workgroup, waves = its waves), 3 matrix-core chains; segmented = 1 for kinds 1 and 2.
+
+        cache: a JSON file of schedules keyed by schedule_key().  A cached schedule is applied without
+        timing (the result then has "cached": True); otherwise, or with retune, the candidates are timed
+        and the winner is stored in the file."""
+        import json
+        key = self.schedule_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+        if cache and not retune and key in table:
+            sched = dict(table[key])
+            try:
+                self.set_schedule(sched)
+                sched["cached"] = True
+                return sched
+            except HelmError:
+                pass                          # not runnable here (other library build): time again
         ks, wv, sg, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
         _check(_lib.helm_batch_tune(self._h, int(reps), C.c_void_p(_stream(stream)), C.byref(ks), C.byref(wv),
                                     C.byref(sg), C.byref(ms)))
-        return {"kind": sg.value, "segmented": 1 if sg.value else 0, "ksplit": ks.value, "waves": wv.value,
-                "ms_per_apply": ms.value}
+        sched = {"kind": sg.value, "segmented": 1 if sg.value in (1, 2) else 0, "ksplit": ks.value,
+                 "waves": wv.value, "ms_per_apply": ms.value}
+        if cache:
+            table[key] = sched
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return sched
 
     def refactor(self, stream=None):
         """Recompute the factors of every member in place (a2 over the whole batch, two launches)."""
