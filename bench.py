@@ -122,22 +122,28 @@ def timed(runner, torch, steps, warmup):
     return (t1 - t0) / steps, phases
 
 
-def copy_bandwidth(torch, gib=2):
-    """Measured HBM bandwidth of a plain device copy (read + write bytes / time, best of 5), GB/s."""
+def copy_bandwidth(torch, hs, gib=1):
+    """Measured HBM bandwidth, read + write bytes / time, best of 5, GB/s: of a plain torch device copy
+    ("torch"), and of the library's calibration copy (helm_calib_copy, a copy of known size) with 16-
+    and with 8-byte accesses -- the kernels whose traffic counters scale the profiled counters to bytes."""
     a = torch.ones(gib * 2**27, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    best = 1e30
-    for _ in range(6):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.copy_(a)
-        e1.record()
-        e1.synchronize()
-        best = min(best, e0.elapsed_time(e1) * 1e-3)
-    nbytes = 2 * a.numel() * 8
+    out = {}
+    for name, fn in (("torch", lambda: b.copy_(a)), (16, lambda: hs.calib_copy(a, b, 16)),
+                     (8, lambda: hs.calib_copy(a, b, 8))):
+        best = 1e30
+        for _ in range(6):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e-3)
+        out[name] = 2 * a.numel() * 8 / best / 1e9
+    assert bool((b == a).all())
     del a, b
     torch.cuda.empty_cache()
-    return nbytes / best / 1e9
+    return out
 
 
 def mfma_flops(probs, B):
@@ -182,7 +188,7 @@ def sweep_bytes_flops(probs, B, fac_bytes, moving_only):
     return by, fl
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_chains_batched96_c64_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_chainC_batched96_c64_traffic.json")
 
 
 def measured_traffic(workload, prec_name, kind):
@@ -381,9 +387,11 @@ def main():
         roof["frac_fp32_vector"] = round(roof["tflops"] / 157.3, 5)      # of the 157.3 TFLOP/s FP32 vector peak
         roof["bytes_formula"] = ("per launch: sum over problems of (strips solved) x 2 passes x n x B(B+1)/2 x "
                                  f"{fac_b} B + N x R x {fac_b} B")
-        hbm_meas = copy_bandwidth(torch)
-        roof["measured_copy_gbs"] = round(hbm_meas, 1)
-        roof["frac_of_measured_copy"] = round(achieved / hbm_meas, 5)
+        cb = copy_bandwidth(torch, hs)
+        roof["measured_copy_gbs"] = round(cb["torch"], 1)     # plain device copy (torch)
+        roof["calib_copy16_gbs"] = round(cb[16], 1)           # helm_calib_copy, 16-byte accesses
+        roof["calib_copy8_gbs"] = round(cb[8], 1)             # the same with 8-byte accesses
+        roof["frac_of_measured_copy"] = round(achieved / cb["torch"], 5)
     else:
         roof["flops_formula"] = ("per launch: sum over chains (problem, front, 16 right-hand sides) of strips x "
                                  "(2n - 1) columns x 6 MFMA x (16-row tiles)^2 x 16 x 16 x 32 x 2")

@@ -249,6 +249,12 @@ int sweep_refactor_batch(helm_batch_t b, void* stream);
 int helm_timing_enable(int32_t on);
 int helm_timing_read(double* ms, int64_t* launches, int32_t reset);
 
+/* Measurement hook (row d): copy `bytes` (a multiple of `width`) from device buffer src to device
+ * buffer dst (not overlapping) with loads and stores of `width` bytes per lane (8 or 16): a kernel
+ * that moves exactly the bytes it is given, against which hardware traffic counters (bytes fetched
+ * from and written to HBM per dispatch) are scaled.  Asynchronous; HELM_EINVAL for other widths. */
+int helm_calib_copy(const void* src, void* dst, int64_t bytes, int32_t width, void* stream);
+
 void helm_free(helm_problem_t A);
 void sweep_free(sweep_factors_t M);
 void helm_batch_free(helm_batch_t b);

@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhelmsweep.so")
 
 SOURCES = ["hs_assemble.hip", "hs_factor.hip", "hs_sweep.hip", "hs_sweep2.hip", "hs_sweepP.hip", "hs_chainc.hip", "hs_chainm.hip", "hs_krylov.hip",
-           "hs_noalloc.hip", "hs_api.cpp"]
+           "hs_noalloc.hip", "hs_calib.hip", "hs_api.cpp"]
 
 
 def hipcc() -> str:

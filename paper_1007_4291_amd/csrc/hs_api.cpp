@@ -1458,6 +1458,15 @@ extern "C" int helm_batch_tune(helm_batch_t b, int32_t reps, void* stream, int32
     return HELM_OK;
 }
 
+extern "C" int helm_calib_copy(const void* src, void* dst, int64_t bytes, int32_t width, void* stream) {
+    if (!src || !dst) return fail(HELM_EINVAL, "NULL argument");
+    if ((width != 8 && width != 16) || bytes < 0 || bytes % width)
+        return fail(HELM_EINVAL, "width must be 8 or 16 and divide bytes");
+    if (!launch_calib_copy(src, dst, bytes, width, (hipStream_t)stream)) return fail(HELM_EINVAL, "width %d", width);
+    LAUNCHCHK();
+    return HELM_OK;
+}
+
 extern "C" int helm_batch_set_schedule(helm_batch_t b, int32_t kind, int32_t ksplit, int32_t waves) {
     if (!b) return fail(HELM_EINVAL, "NULL argument");
     const int q = chain_rhs_per_wave(b->B);

@@ -201,6 +201,9 @@ bool launch_msplit(int B, const void* fac, void* msp, int64_t ncols, hipStream_t
 bool launch_chains_mfma(int B, int in_prec, int out_prec, int phase, const ProbDev* probs, const ChainDev* chains,
                         int nchains, const IoDev* io, IoDev io_val, void* ws, const int32_t* active, hipStream_t s);
 
+// Copy of `bytes` (a multiple of width) from src to dst with width-byte loads and stores (8 or 16).
+bool launch_calib_copy(const void* src, void* dst, int64_t bytes, int width, hipStream_t s);
+
 // Device address of the allocation-free entry point's static scratch array on the current device
 // (looked up once per device), or nullptr with noalloc_error() set.
 void* noalloc_scratch();

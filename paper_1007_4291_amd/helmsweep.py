@@ -30,7 +30,7 @@ EXPORTS = ["helm_version", "helm_last_error", "helm_assemble", "helm_reassemble"
            "sweep_factor", "sweep_refactor", "sweep_factor_bytes", "sweep_apply", "sweep_apply_noalloc", "sweep_subsolve", "sweep_num_subproblems", "sweep_subproblem_rows",
            "fgmres_solve", "helm_batch_create", "fgmres_solve_batch", "sweep_apply_batch", "sweep_refactor_batch", "helm_batch_tune", "helm_batch_set_schedule",
            "helm_batch_set_graph", "helm_free", "sweep_free",
-           "helm_batch_free", "helm_timing_enable", "helm_timing_read"]
+           "helm_batch_free", "helm_timing_enable", "helm_timing_read", "helm_calib_copy"]
 PHASES = ["assemble", "factor", "sweep_fwd", "sweep_mid", "sweep_bwd", "matvec", "krylov", "sweep_front"]
 
 
@@ -75,6 +75,7 @@ def _load() -> C.CDLL:
                                       C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "helm_batch_set_graph": (C.c_int, [vp, C.c_int32]),
         "helm_batch_set_schedule": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32]),
+        "helm_calib_copy": (C.c_int, [vp, vp, C.c_int64, C.c_int32, vp]),
         "helm_free": (None, [vp]),
         "sweep_free": (None, [vp]),
         "helm_batch_free": (None, [vp]),
@@ -435,3 +436,12 @@ class Batch:
         if h is not None and h.value:
             _lib.helm_batch_free(h)
             self._h = None
+
+
+def calib_copy(src, dst, width: int, stream=None):
+    """Measurement hook: copy the bytes of device tensor src into dst with width-byte (8 or 16) accesses."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst must have the same size in bytes")
+    _check(_lib.helm_calib_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, int(width),
+                                C.c_void_p(_stream(stream))))
