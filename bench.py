@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched", choices=["batched", "lens255", "grf1023", "const63", "waveguide2047"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "lens255", "grf1023", "const63", "waveguide2047",
+                                                            "waveguide255"])
     ap.add_argument("--prec", default="c64", choices=["c64", "c128", "bf16x3"],
                     help="factor precision and sweep arithmetic (bf16x3: the matrix-core block products)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 comparison (0: skip)")
@@ -63,6 +64,10 @@ def build_workload(name: str, per_size: int):
     elif name == "grf1023":
         probs = [W.cfg3()]
         desc = "n=1023, omega/2pi=128, Gaussian random velocity, Gaussian source, widths 12, FGMRES(20) to 1e-6"
+    elif name == "waveguide255":
+        probs = [W.cfg5(n=255, freq=32.0)]
+        desc = ("n=255, omega/2pi=32, waveguide velocity, 64 point sources on row 26, widths 16 (B=17), "
+                "FGMRES(30) to 1e-6 (the n=2047 waveguide problem's generator at n=255)")
     elif name == "waveguide2047":
         probs = [W.cfg5()]
         desc = ("n=2047, omega/2pi=256, waveguide velocity, 64 point sources on row 205, widths 16 (B=17), "
@@ -450,7 +455,7 @@ def main():
             out["fp64"] = {"skipped": str(e)[:300]}
             print(f"[bench] c128 leg skipped: {e}", file=sys.stderr, flush=True)
 
-    if a.workload == "waveguide2047":
+    if a.workload in ("waveguide2047", "waveguide255"):
         out["cpu_baseline"] = {"value": None, "kind": "oracle", "skipped": (
             "one system of this workload takes the oracle several minutes (about 2000 strip factorisations and "
             "15 FGMRES iterations of 2000 banded strip solves each), beyond the bounded sample this line allows")}
