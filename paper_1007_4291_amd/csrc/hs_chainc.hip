@@ -65,13 +65,15 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
                                                            const CompDev* __restrict__ work) {
     using SH = CompShape<BS, SEG>;
     constexpr int P = SEG + BS;                       // unit inputs: gamma_0..gamma_{SEG-1}, c_in e_0..e_{B-1}
+    constexpr int PT = (P + 2) / 3 * 3;               // ... padded to whole triples of columns (zero columns)
+    constexpr int TT = PT / 3;
+    constexpr int NGT = TT * (TT + 1) / 2;            // 3 x 3 tiles of the upper triangle of the symmetric G
     constexpr int PACK = packed_size(BS), STRIDE = col_stride<TF>(BS);
-    constexpr int NZ = BS * P;
-    constexpr int NG = P * (P + 1) / 2;               // upper triangle of the symmetric G
-    constexpr int GPT = (NG + COMP_THREADS - 1) / COMP_THREADS;
     constexpr int SLOT = BS - 1;                      // the layer row (local row order)
-    __shared__ double2 zs[BS][P];
-    __shared__ double2 ys[BS][P];
+    static_assert(NGT <= COMP_THREADS && BS * TT <= COMP_THREADS, "one thread per tile");
+    // LDS: the z and y = Lambda^{-1} z vectors of all unit inputs (FP64), the step's Lambda^{-1}, -E/s2
+    __shared__ double2 zs[BS][PT];
+    __shared__ double2 ys[BS][PT];
     __shared__ double2 lam[BS][BS];
     __shared__ double2 ne[BS];                        // -E_t / s2 of each row for the current step
     __shared__ float2 cpl[SEG][2];
@@ -83,23 +85,26 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
     const int tb = (W.cdir > 0) ? W.seg * SEG : n - W.seg * SEG - SEG;   // LU step of local step 0
     const HS_GLOBAL C2<TF>* fac = gptr((const C2<TF>*)W.fac);
 
-    for (int e = tid; e < NZ; e += COMP_THREADS) {
-        const int r = e / P, p = e - (e / P) * P;
-        zs[r][p] = make_double2((p >= SEG && p - SEG == r) ? 1.0 : 0.0, 0.0);
+    for (int e = tid; e < BS * PT; e += COMP_THREADS) {
+        const int r = e / PT, p = e - (e / PT) * PT;
+        zs[r][p] = make_double2((p >= SEG && p < P && p - SEG == r) ? 1.0 : 0.0, 0.0);
     }
     for (int e = tid; e < 2 * SEG; e += COMP_THREADS) cpl[e >> 1][e & 1] = make_float2(0.f, 0.f);
-    int ga[GPT], gb[GPT];
-#pragma unroll
-    for (int u = 0; u < GPT; ++u) {
-        int g = tid + u * COMP_THREADS, a = 0;
-        if (g >= NG) g = NG - 1;
-        while (g >= P - a) { g -= P - a; ++a; }
-        ga[u] = a;
-        gb[u] = a + g;
+    // register tiles: the G tile (rows 3 gi .., columns 3 gj ..) and the y tile (row yr, columns 3 yt ..)
+    // of this thread, so that every LDS value read feeds three multiply-adds
+    int gi = 0, gj = 0;
+    if (tid < NGT) {
+        int g = tid, a = 0;
+        while (g >= TT - a) { g -= TT - a; ++a; }
+        gi = a;
+        gj = a + g;
     }
-    double2 gacc[GPT];
+    const int yr = tid / TT, yt = tid - (tid / TT) * TT;
+    double2 gacc[3][3];
 #pragma unroll
-    for (int u = 0; u < GPT; ++u) gacc[u] = make_double2(0.0, 0.0);
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gacc[i][k] = make_double2(0.0, 0.0);
     // packed index -> (row, column) of this thread's entry of the stored column
     int pr = 0, pk = 0;
     if (tid < PACK) {
@@ -130,35 +135,57 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
         }
         if (tid == 0) zs[SLOT][j] = make_double2(1.0, 0.0);   // gamma_j enters at its own step
         __syncthreads();
-        for (int e = tid; e < NZ; e += COMP_THREADS) {
-            const int r = e / P, p = e - (e / P) * P;
-            double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 4
-            for (int k = 0; k < BS; ++k) acc = cfma<double>(lam[r][k], zs[k][p], acc);
-            ys[r][p] = acc;
-        }
-        __syncthreads();
+        // y = Lambda^{-1} z, a row and three columns per thread
+        if (tid < BS * TT) {
+            double2 acc[3];
 #pragma unroll
-        for (int u = 0; u < GPT; ++u) {
-            double2 acc = gacc[u];
-#pragma unroll 2
-            for (int r = 0; r < BS; ++r) acc = cfma<double>(zs[r][ga[u]], ys[r][gb[u]], acc);
-            gacc[u] = acc;
+            for (int c = 0; c < 3; ++c) acc[c] = make_double2(0.0, 0.0);
+#pragma unroll 4
+            for (int k = 0; k < BS; ++k) {
+                const double2 l = lam[yr][k];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[c] = cfma<double>(l, zs[k][3 * yt + c], acc[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ys[yr][3 * yt + c] = acc[c];
         }
         __syncthreads();
-        for (int e = tid; e < NZ; e += COMP_THREADS) {
-            const int r = e / P, p = e - (e / P) * P;
+        // G += z^T y over the step, a 3 x 3 tile per thread
+        if (tid < NGT) {
+#pragma unroll 2
+            for (int r = 0; r < BS; ++r) {
+                double2 za[3], yb[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    za[c] = zs[r][3 * gi + c];
+                    yb[c] = ys[r][3 * gj + c];
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) gacc[i][k] = cfma<double>(za[i], yb[k], gacc[i][k]);
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < BS * PT; e += COMP_THREADS) {
+            const int r = e / PT, p = e - (e / PT) * PT;
             zs[r][p] = cmul<double>(ne[r], ys[r][p]);
         }
         __syncthreads();
     }
+    // G's upper triangle (a <= b) from the tiles, mirrored
+    if (tid < NGT) {
 #pragma unroll
-    for (int u = 0; u < GPT; ++u) {
-        if (tid + u * COMP_THREADS < NG) {
-            const float2 v = make_float2((float)gacc[u].x, (float)gacc[u].y);
-            gram[ga[u]][gb[u]] = v;
-            gram[gb[u]][ga[u]] = v;
-        }
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int a = 3 * gi + i, b = 3 * gj + k;
+                if (a < P && b < P && a <= b) {
+                    const float2 v = make_float2((float)gacc[i][k].x, (float)gacc[i][k].y);
+                    gram[a][b] = v;
+                    gram[b][a] = v;
+                }
+            }
     }
     __syncthreads();
     HS_GLOBAL float2* out = gptr((float2*)W.out);
