@@ -250,6 +250,38 @@ __device__ __forceinline__ void lds_stage(float2* dst, const HS_GLOBAL float2* s
 }
 __device__ __forceinline__ void lds_stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Hand-off between the waves of a chain through LDS flags that carry the strip count: a producer
+// publishes its LDS data, then the flag (release); a consumer waits for the flag (acquire).  The wait
+// is bounded (about 4 M cycles): a hand-off that never comes ends the wait -- wrong results, which the
+// parity tests see, rather than a hung device.
+// The flag index is made opaque, so that its LDS address is formed at the use rather than hoisted
+// out of the strip loop into a register held across it.
+__device__ __forceinline__ void flag_set(int* f, int idx, int v) {
+    asm volatile("" : "+v"(idx));
+    __hip_atomic_store(f + idx, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void flag_wait(const int* f, int idx, int v) {
+    asm volatile("" : "+v"(idx));
+    for (int spin = 0; spin < (1 << 16); ++spin) {
+        if (__hip_atomic_load(f + idx, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= v) return;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Waits for NF flags spaced by stride (one per producing wave) in one bounded loop.
+template <int NF>
+__device__ __forceinline__ void flag_wait_all(const int* f, int idx, int stride, int v) {
+    asm volatile("" : "+v"(idx));
+    for (int spin = 0; spin < (1 << 16); ++spin) {
+        bool ok = true;
+#pragma unroll
+        for (int w = 0; w < NF; ++w)
+            ok = ok && __hip_atomic_load(f + idx + w * stride, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= v;
+        if (ok) return;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 template <int BS, int SEG, int MODE, class TI, class TO, int RQ>
 __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ probs, const ChainDev* __restrict__ chains,
                                                  const IoDev* __restrict__ io, IoDev io_val,
@@ -267,6 +299,15 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     float2* const xab = cin + nwv * LS::VEC;
     float2* const phl = xab + nwv * LS::VEC;            // [nwv][PHIP]: Phi of each segment, row-major
     float2* const stg = phl + nwv * LS::PHIP;           // [nwv][STG]: G2, then G3, of each segment
+    constexpr int NSW = RQ / 2;                         // spine waves (the launch has at least as many)
+    // ready flags (strip count): qf and qb of each segment (its wave), c_in and x_above of each segment
+    // (per spine wave: each writes its own right-hand sides)
+    int* const f_qf = (int*)(stg + nwv * LS::STG);
+    int* const f_qb = f_qf + nwv;
+    int* const f_cin = f_qb + nwv;                      // [NSW][nwv]
+    int* const f_xab = f_cin + NSW * nwv;               // [NSW][nwv]
+    for (int e = threadIdx.x; e < (2 + 2 * NSW) * nwv; e += blockDim.x) f_qf[e] = 0;
+    __syncthreads();
 
     const ChainDev ch = chains[blockIdx.x];
     if (ch.nq == 0) return;
@@ -278,13 +319,8 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index: uniform
     int lane = threadIdx.x & 63;      // made opaque at every strip (below): per-lane offsets are recomputed
                                       // in the strip loop rather than held in registers across it
-    constexpr int NSW = RQ / 2;                        // spine waves (the launch has at least as many)
     const bool segw = wv < S;                          // this wave has a segment of the strips
-    if (!segw && wv >= NSW) {
-        // neither a segment nor a spine for this wave: take part in the chain's barriers, then leave
-        for (int b = 0; b < 4 * L; ++b) __syncthreads();
-        return;
-    }
+    if (!segw && wv >= NSW) return;                    // neither a segment nor a spine for this wave
     const IoDev IO = io ? io[ch.prob] : io_val;
     const int64_t N = (int64_t)n * n;
     const int dirF = ch.front == 0 ? 1 : -1;
@@ -305,7 +341,8 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     // terms, kk = KH half + j (j < KH): v[kk] comes by DPP row broadcast from lane j of a copy of v that is
     // rotated by KH lanes in the upper half, and the two halves are added across lanes l and l ^ 32.  The
     // next segment's matrix row and addends are read from LDS at the top of each step, under its products.
-    auto spine = [&](int mat, bool up, const float2* addv, float2* store) __attribute__((always_inline)) {
+    auto spine = [&](int mat, bool up, const float2* addv, float2* store, const int* f_in, int* f_out, int tgt)
+        __attribute__((always_inline)) {
         constexpr int KH = (BS + 1) / 2;
         constexpr int NA = 2;                           // independent partial sums
         const int r = lane & 15, half = lane >> 5, q = 2 * wv + ((lane >> 4) & 1);
@@ -322,6 +359,8 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
             for (int j = 0; j < KH; ++j) dst[j] = pbase[ss * LS::PHIP + j * pstep];
         };
         float2 v = make_float2(0.f, 0.f), ad, pr[KH], pr2[KH];
+        // a segment's flag publishes its Phi and addends together: wait before reading either
+        flag_wait(f_in, seg_at(0), tgt);
         load_row(seg_at(0), pr);
         ad = addv[(seg_at(0) * BS + rr) * RQ + q];
         // lanes that store nothing (upper half, rows past the block) write a spare slot: the padding of
@@ -329,6 +368,7 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
         float2* const spare = phl + BS * BS;
         auto step = [&](int k, float2 (&cur)[KH], float2 (&nxt)[KH]) __attribute__((always_inline)) {
             const int ss = seg_at(k), sn = seg_at(k + 1 < S ? k + 1 : k);
+            flag_wait(f_in, sn, tgt);                  // the next segment's Phi and addends are published
             load_row(sn, nxt);
             const float2 adn = addv[(sn * BS + rr) * RQ + q];
             __builtin_amdgcn_sched_barrier(0);
@@ -356,9 +396,14 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
             ad = adn;
             // the value entering the next segment, stored now: its register is not rewritten until the
             // end of the next step, so the store never holds up a step
-            if (k + 1 < S) *(half == 0 && r < BS ? &store[(sn * BS + r) * RQ + q] : spare) = v;
+            if (k + 1 < S) {
+                *(half == 0 && r < BS ? &store[(sn * BS + r) * RQ + q] : spare) = v;
+                if (lane == 0) flag_set(f_out, sn, tgt);
+            }
+            (void)ss;
         };
         *(half == 0 && r < BS ? &store[(seg_at(0) * BS + r) * RQ + q] : spare) = v;
+        if (lane == 0) flag_set(f_out, seg_at(0), tgt);
         for (int k = 0; k < S; k += 2) {       // two steps per pass: the row buffers swap roles, no copies
             step(k, pr, pr2);
             if (k + 1 < S) step(k + 1, pr2, pr);
@@ -482,13 +527,14 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
                     for (int q = 0; q < RQ; ++q) gs[cc * RQ + q] = acc[q];
                 }
             }
+            if (lane == 0) flag_set(f_qf, s, i + 1);      // qf, qb and Phi of this segment are in LDS
         }
-        __syncthreads();
-        // ---- 2. forward spine (waves 0 .. NSW - 1): carries entering every segment, in the strip's LU order
-        if (wv < NSW) spine(0, cd > 0, qf, cin);
-        __syncthreads();
+        // ---- 2. forward spine (waves 0 .. NSW - 1): carries entering every segment, in the strip's LU order;
+        // it takes each segment's qf as soon as it is published and publishes each c_in
+        if (wv < NSW) spine(0, cd > 0, qf, cin, f_qf, f_cin + wv * nwv, i + 1);
         if (segw) {
             // ---- 3. qb += W c_in, y += VS c_in
+            flag_wait_all<NSW>(f_cin, s, nwv, i + 1);
             lds_stage_wait();
             if (l3) {
                 float2 acc[RQ];
@@ -509,6 +555,7 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
             // the x_above block G3 and, in the backward phase, the current values of the output row, to arrive
             // during the backward spine
             wave_sync();              // every lane of the wave has read G2: G3 takes its place
+            if (lane == 0) flag_set(f_qb, s, i + 1);      // qb of this segment is final
             lds_stage<BS * SH::R3P>(stg_s, blk + SH::O_G3, lane);
             if constexpr (MODE == MODE_BWD) {
     #pragma unroll
@@ -520,11 +567,12 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
                 }
             }
         }
-        __syncthreads();
-        // ---- 4. backward spine (waves 0 .. NSW - 1): values entering every segment from above, reverse LU order
-        if (wv < NSW) spine(1, cd < 0, qb, xab);
-        __syncthreads();
+        // ---- 4. backward spine (waves 0 .. NSW - 1): values entering every segment from above, reverse LU
+        // order, segment by segment as their qb are published
+        if (wv < NSW) spine(1, cd < 0, qb, xab, f_qb, f_xab + wv * nwv, i + 1);
         if (segw) {
+            // x_above of this segment is in LDS, and the spines have read this segment's Phi and qb
+            flag_wait_all<NSW>(f_xab, s, nwv, i + 1);
             // ---- the next strip's first group (the last strip re-requests its own: a fixed count)
             request(i + 1 < L ? i + 1 : i);
             // ---- 5. y += US x_above; the strip's layer-row output
@@ -593,12 +641,12 @@ bool launch_compress(int B, int seg, int prec, const ProbDev* probs, const CompD
 }
 
 size_t chainc_lds_bytes(int B, int seg, int rq, int waves) {
-    // ChainCShape<B, seg, rq>::PER_SEG per wave
+    // ChainCShape<B, seg, rq>::PER_SEG per wave, then the ready flags: (2 + 2 rq / 2) ints per wave
     const int r2p = (B + seg + 15) & ~15, r3p = (seg + 15) & ~15;
     const int phip = (B * B + 127) & ~127;
     const int stg = ((B * r2p > B * r3p ? B * r2p : B * r3p) + 127) & ~127;
     const int per = seg * rq + 4 * B * rq + phip + stg;
-    return (size_t)per * waves * sizeof(float2);
+    return (size_t)per * waves * sizeof(float2) + (size_t)(2 + rq) * waves * sizeof(int);
 }
 
 template <int BS, int SEG, int MODE, class TI, class TO, int RQ>
