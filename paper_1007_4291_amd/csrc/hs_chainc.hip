@@ -335,17 +335,17 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     float2* const stg_s = stg + s * LS::STG;
 
     // A spine: v <- Mat_ss v + add_ss over the segments ss in LU order (up) or reverse LU order, storing
-    // the value entering each segment in store[ss]; Mat = Phi (mat 0) or Phi^T (mat 1).  Waves
-    // 0 .. RQ/2 - 1 take two right-hand sides each.  Lane (half, p, r) = (lane >> 5, (lane >> 4) & 1,
-    // lane & 15) holds row r of right-hand side q = 2 wv + p and sums Mat[r][kk] v[kk] over its half of the
+    // the value entering each segment in store[ss]; Mat = Phi (mat 0) or Phi^T (mat 1).  The waves of
+    // spine rank sr = 0 .. RQ/2 - 1 take two right-hand sides each.  Lane (half, p, r) = (lane >> 5,
+    // (lane >> 4) & 1, lane & 15) holds row r of right-hand side q = 2 sr + p and sums Mat[r][kk] v[kk] over its half of the
     // terms, kk = KH half + j (j < KH): v[kk] comes by DPP row broadcast from lane j of a copy of v that is
     // rotated by KH lanes in the upper half, and the two halves are added across lanes l and l ^ 32.  The
     // next segment's matrix row and addends are read from LDS at the top of each step, under its products.
-    auto spine = [&](int mat, bool up, const float2* addv, float2* store, const int* f_in, int* f_out, int tgt)
-        __attribute__((always_inline)) {
+    auto spine = [&](int mat, bool up, const float2* addv, float2* store, const int* f_in, int* f_out, int tgt,
+                     int sr) __attribute__((always_inline)) {
         constexpr int KH = (BS + 1) / 2;
         constexpr int NA = 2;                           // independent partial sums
-        const int r = lane & 15, half = lane >> 5, q = 2 * wv + ((lane >> 4) & 1);
+        const int r = lane & 15, half = lane >> 5, q = 2 * sr + ((lane >> 4) & 1);
         const int rr = r < BS ? r : BS - 1, kk0 = KH * half;
         auto seg_at = [&](int k) { return up ? k : S - 1 - k; };
         // Mat[r][kk0 + j] of segment ss at pbase + ss * PHIP + j * pstep.  Past the block (kk0 + j >= BS)
@@ -366,6 +366,8 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
         // lanes that store nothing (upper half, rows past the block) write a spare slot: the padding of
         // segment 0's Phi area
         float2* const spare = phl + BS * BS;
+        // the spine is the strip's critical path: its wave issues ahead of the segment waves on its SIMD
+        __builtin_amdgcn_s_setprio(2);
         auto step = [&](int k, float2 (&cur)[KH], float2 (&nxt)[KH]) __attribute__((always_inline)) {
             const int ss = seg_at(k), sn = seg_at(k + 1 < S ? k + 1 : k);
             flag_wait(f_in, sn, tgt);                  // the next segment's Phi and addends are published
@@ -408,6 +410,7 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
             step(k, pr, pr2);
             if (k + 1 < S) step(k + 1, pr2, pr);
         }
+        __builtin_amdgcn_s_setprio(0);
     };
 
     // Global data of a strip is requested in three groups, each a phase ahead of its use: after the
@@ -529,9 +532,15 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
             }
             if (lane == 0) flag_set(f_qf, s, i + 1);      // qf, qb and Phi of this segment are in LDS
         }
-        // ---- 2. forward spine (waves 0 .. NSW - 1): carries entering every segment, in the strip's LU order;
-        // it takes each segment's qf as soon as it is published and publishes each c_in
-        if (wv < NSW) spine(0, cd > 0, qf, cin, f_qf, f_cin + wv * nwv, i + 1);
+        // Both spines of the strip run on the waves of the first NSW segments in its LU order (waves without
+        // a segment keep their index as spine rank).  Those segments are the last to receive x_above in
+        // the previous strip's backward spine and the first to receive c_in here, so their waves are free
+        // when this strip's forward spine can begin, and the next strip's spines, which begin at the other
+        // end, run on other waves while this strip's backward spine is still going.
+        const int sr = segw ? (cd > 0 ? wv : S - 1 - wv) : wv;
+        // ---- 2. forward spine: carries entering every segment, in the strip's LU order; it takes each
+        // segment's qf as soon as it is published and publishes each c_in
+        if (sr < NSW) spine(0, cd > 0, qf, cin, f_qf, f_cin + sr * nwv, i + 1, sr);
         if (segw) {
             // ---- 3. qb += W c_in, y += VS c_in
             flag_wait_all<NSW>(f_cin, s, nwv, i + 1);
@@ -567,9 +576,9 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
                 }
             }
         }
-        // ---- 4. backward spine (waves 0 .. NSW - 1): values entering every segment from above, reverse LU
+        // ---- 4. backward spine: values entering every segment from above, reverse LU
         // order, segment by segment as their qb are published
-        if (wv < NSW) spine(1, cd < 0, qb, xab, f_qb, f_xab + wv * nwv, i + 1);
+        if (sr < NSW) spine(1, cd < 0, qb, xab, f_qb, f_xab + sr * nwv, i + 1, sr);
         if (segw) {
             // x_above of this segment is in LDS, and the spines have read this segment's Phi and qb
             flag_wait_all<NSW>(f_xab, s, nwv, i + 1);
