@@ -413,11 +413,12 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
         __builtin_amdgcn_s_setprio(0);
     };
 
-    // Global data of a strip is requested in three groups, each a phase ahead of its use: after the
-    // previous strip's backward spine its couplings, input row, Phi (straight to LDS) and the gamma columns
-    // G1 (in the order they are consumed), which arrive during the previous strip's phase 5; after phase 1
-    // the c_in block G2 (straight to LDS), which arrives during the forward spine; after phase 3 the
-    // x_above block G3 (to LDS, in G2's place) and, backward, the output row, which arrive during the
+    // Global data of a strip is requested in three groups, each a phase ahead of its use.  The first: its
+    // couplings, input row and the gamma columns G1 (to registers, in the order they are consumed), right
+    // after the previous strip's phase 3 (on the spine waves after the backward spine, which needs their
+    // registers), then Phi (straight to LDS) once the backward spine has read the previous Phi.  After
+    // phase 1 the c_in block G2 (straight to LDS), which arrives during the forward spine; after phase 3
+    // the x_above block G3 (to LDS, in G2's place) and, backward, the output row, which arrive during the
     // backward spine.  Every group issues a fixed number of loads (masked lanes read a valid address), so
     // that a wait for "all but the next strip's first group" is an exact vmcnt.
     auto strip_of = [&](int i) { return MODE == MODE_FWD ? i + 1 : L - i; };     // strip index in its front
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     constexpr int NREQ = 1 + (MODE == MODE_FWD ? NH0 : 0) + (BS * BS + 127) / 128 + SEG;   // loads of a first group
     float2 cpl_v, g1[SEG];
     double2 fin_v[NH0];
-    // the first group of strip i (i < L)
+    // the first group of strip i (i < L): registers, then Phi
     auto request = [&](int i) __attribute__((always_inline)) {
         const int st = strip_of(i), cd = (st & 1) ? -1 : 1;
         const HS_GLOBAL float2* const blk = strip_blk(i);
@@ -456,12 +457,14 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
                 fin_v[h] = ok ? f : make_double2(0.0, 0.0);
             }
         }
-        lds_stage<BS * BS>(phl + s * LS::PHIP, blk + SH::O_PHI, lane);
         const uint32_t v1 = (uint32_t)(SH::O_G1 + (lane < SH::R1P ? lane : 0)) * 8u;
 #pragma unroll
         for (int j = 0; j < SEG; ++j) buf_ld(g1[j], rs, v1, (uint32_t)(j * SH::R1P) * 8u);
     };
-    if (segw) request(0);
+    auto request_phi = [&](int i) __attribute__((always_inline)) {
+        lds_stage<BS * BS>(phl + s * LS::PHIP, strip_blk(i) + SH::O_PHI, lane);
+    };
+    if (segw) { request(0); request_phi(0); }
     for (int i = 0; i < L; ++i) {
         asm volatile("" : "+v"(lane));
         lane_roles();
@@ -513,8 +516,8 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
                     });
                     __builtin_amdgcn_sched_barrier(0);
                 });
-                // Phi is in LDS (it was requested before G1, all of which has been used); then the c_in block,
-                // to arrive during the forward spine
+                // Phi is in LDS (the wait drains the first group: G1 has been used, Phi came last); then the
+                // c_in block, to arrive during the forward spine
                 lds_stage_wait();
                 lds_stage<BS * SH::R2P>(stg_s, blk + SH::O_G2, lane);
                 wave_sync();          // every lane has read gamma: the layer-row values y take its place
@@ -578,12 +581,14 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
         }
         // ---- 4. backward spine: values entering every segment from above, reverse LU
         // order, segment by segment as their qb are published
+        if (segw && sr >= NSW) request(i + 1 < L ? i + 1 : i);    // the next strip's G1 and input, early
         if (sr < NSW) spine(1, cd < 0, qb, xab, f_qb, f_xab + sr * nwv, i + 1, sr);
         if (segw) {
             // x_above of this segment is in LDS, and the spines have read this segment's Phi and qb
             flag_wait_all<NSW>(f_xab, s, nwv, i + 1);
-            // ---- the next strip's first group (the last strip re-requests its own: a fixed count)
-            request(i + 1 < L ? i + 1 : i);
+            // ---- the rest of the next strip's first group (the last strip re-requests its own: a fixed count)
+            if (sr < NSW) request(i + 1 < L ? i + 1 : i);
+            request_phi(i + 1 < L ? i + 1 : i);
             // ---- 5. y += US x_above; the strip's layer-row output
             asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NREQ) : "memory");   // G3 (and the output row) have landed
             if (lane >= 2 * BS && lane < SH::R1) {
