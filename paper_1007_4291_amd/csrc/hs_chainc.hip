@@ -237,35 +237,48 @@ template <int BS, int SEG, int RQ> struct ChainCShape {
 // wave's LDS area dst (room for LEN rounded up to 128): chunk u of lane l moves values 128u + 2l and
 // 128u + 2l + 1 (one 16-byte global-to-LDS load per lane and chunk, written at the lane's own 16 bytes of
 // the chunk).  Lanes past the end re-read the first pair, into the padding.  The data is in LDS once
-// vmcnt has drained (lds_stage_wait).
+// vmcnt has drained (lds_stage_wait, or an exact vmcnt that covers the copy).
+// The copies are issued from inline assembly, out of the compiler's sight: it would otherwise wait for
+// every copy in flight (vmcnt(0)) before any later LDS read, since it cannot tell which LDS words a copy
+// writes -- which would put a global-memory round trip in front of the spines and of phase 5.  Every
+// read of staged data here follows an explicit wait; a compiler-placed vmcnt for a register load only
+// gets stricter from copies it does not count.  The LDS base goes in M0, which needs one wait state
+// before the copy.
 template <int LEN>
 __device__ __forceinline__ void lds_stage(float2* dst, const HS_GLOBAL float2* src, int lane) {
     constexpr int NCH = (LEN + 127) / 128;
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float2*)dst);
 #pragma unroll
     for (int u = 0; u < NCH; ++u) {
         const int e = 128 * u + 2 * lane;
-        __builtin_amdgcn_global_load_lds((const HS_GLOBAL void*)(src + (e < LEN ? e : 0)),
-                                         (__attribute__((address_space(3))) void*)(dst + 128 * u), 16, 0, 0);
+        const HS_GLOBAL float2* const p = src + (e < LEN ? e : 0);
+        asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                     :: "v"(p), "s"(d0 + 128u * 8u * u) : "memory", "m0");
     }
 }
 __device__ __forceinline__ void lds_stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Hand-off between the waves of a chain through LDS flags that carry the strip count: a producer
-// publishes its LDS data, then the flag (release); a consumer waits for the flag (acquire).  The wait
-// is bounded (about 4 M cycles): a hand-off that never comes ends the wait -- wrong results, which the
-// parity tests see, rather than a hung device.
+// publishes its LDS data, then the flag (release); a consumer waits for the flag (acquire).  The fences
+// cover LDS only: everything handed over lives in LDS (a global-to-LDS copy that is handed over has been
+// waited for before the flag), and a fence over global memory as well would wait for every load and copy
+// in flight.  The wait is bounded (about 4 M cycles): a hand-off that never comes ends the wait -- wrong
+// results, which the parity tests see, rather than a hung device.
 // The flag index is made opaque, so that its LDS address is formed at the use rather than hoisted
 // out of the strip loop into a register held across it.
 __device__ __forceinline__ void flag_set(int* f, int idx, int v) {
     asm volatile("" : "+v"(idx));
-    __hip_atomic_store(f + idx, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __hip_atomic_store(f + idx, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void flag_wait(const int* f, int idx, int v) {
     asm volatile("" : "+v"(idx));
     for (int spin = 0; spin < (1 << 16); ++spin) {
-        if (__hip_atomic_load(f + idx, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= v) return;
+        if (__hip_atomic_load(f + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= v) break;
         __builtin_amdgcn_s_sleep(1);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Waits for NF flags spaced by stride (one per producing wave) in one bounded loop.
@@ -276,10 +289,11 @@ __device__ __forceinline__ void flag_wait_all(const int* f, int idx, int stride,
         bool ok = true;
 #pragma unroll
         for (int w = 0; w < NF; ++w)
-            ok = ok && __hip_atomic_load(f + idx + w * stride, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= v;
-        if (ok) return;
+            ok = ok && __hip_atomic_load(f + idx + w * stride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= v;
+        if (ok) break;
         __builtin_amdgcn_s_sleep(1);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 template <int BS, int SEG, int MODE, class TI, class TO, int RQ>
@@ -358,7 +372,10 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
 #pragma unroll
             for (int j = 0; j < KH; ++j) dst[j] = pbase[ss * LS::PHIP + j * pstep];
         };
-        float2 v = make_float2(0.f, 0.f), ad, pr[KH], pr2[KH];
+        float2 ad, pr[KH], pr2[KH];
+        float z0 = 0.f;
+        asm volatile("" : "+v"(z0));                    // a zero made here, not held (or spilled) across the strips
+        float2 v = make_float2(z0, z0);
         // a segment's flag publishes its Phi and addends together: wait before reading either
         flag_wait(f_in, seg_at(0), tgt);
         load_row(seg_at(0), pr);
@@ -546,8 +563,25 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
         if (sr < NSW) spine(0, cd > 0, qf, cin, f_qf, f_cin + sr * nwv, i + 1, sr);
         if (segw) {
             // ---- 3. qb += W c_in, y += VS c_in
+            // In the backward phase the current values of the output row are requested first: they arrive
+            // while this segment waits for its c_in.
+            TO uraw[MODE == MODE_BWD ? RQ : 1];
+            if constexpr (MODE == MODE_BWD) {
+    #pragma unroll
+                for (int q = 0; q < RQ; ++q) {
+                    const bool ok = out5 && q < ch.nq;
+                    uraw[q] = gld(uout + (ok ? (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col5 : (int64_t)0));
+                }
+            }
             flag_wait_all<NSW>(f_cin, s, nwv, i + 1);
-            lds_stage_wait();
+            lds_stage_wait();         // G2 is in LDS, and the output row has arrived
+            if constexpr (MODE == MODE_BWD) {
+    #pragma unroll
+                for (int q = 0; q < RQ; ++q) {
+                    const bool ok = out5 && q < ch.nq;
+                    uold[q] = ok ? make_float2((float)uraw[q].x, (float)uraw[q].y) : make_float2(0.f, 0.f);
+                }
+            }
             if (l3) {
                 float2 acc[RQ];
     #pragma unroll
@@ -564,30 +598,21 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     #pragma unroll
                 for (int q = 0; q < RQ; ++q) d[q] = cadd<float>(d[q], acc[q]);
             }
-            // the x_above block G3 and, in the backward phase, the current values of the output row, to arrive
-            // during the backward spine
+            // the x_above block G3, to arrive during the backward spine
             wave_sync();              // every lane of the wave has read G2: G3 takes its place
             if (lane == 0) flag_set(f_qb, s, i + 1);      // qb of this segment is final
             lds_stage<BS * SH::R3P>(stg_s, blk + SH::O_G3, lane);
-            if constexpr (MODE == MODE_BWD) {
-    #pragma unroll
-                for (int q = 0; q < RQ; ++q) {
-                    const bool ok = out5 && q < ch.nq;
-                    const float2 u = ccast<float, double>(
-                        ld2(uout + (ok ? (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col5 : (int64_t)0)));
-                    uold[q] = ok ? u : make_float2(0.f, 0.f);
-                }
-            }
         }
         // ---- 4. backward spine: values entering every segment from above, reverse LU
         // order, segment by segment as their qb are published
-        if (segw && sr >= NSW) request(i + 1 < L ? i + 1 : i);    // the next strip's G1 and input, early
         if (sr < NSW) spine(1, cd < 0, qb, xab, f_qb, f_xab + sr * nwv, i + 1, sr);
         if (segw) {
+            // ---- the next strip's first group (the last strip re-requests its own: a fixed count): the
+            // registers now -- a segment wave without a spine is here right after its phase 3 --, Phi once
+            // the spines have read this segment's Phi
+            request(i + 1 < L ? i + 1 : i);
             // x_above of this segment is in LDS, and the spines have read this segment's Phi and qb
             flag_wait_all<NSW>(f_xab, s, nwv, i + 1);
-            // ---- the rest of the next strip's first group (the last strip re-requests its own: a fixed count)
-            if (sr < NSW) request(i + 1 < L ? i + 1 : i);
             request_phi(i + 1 < L ? i + 1 : i);
             // ---- 5. y += US x_above; the strip's layer-row output
             asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NREQ) : "memory");   // G3 (and the output row) have landed
@@ -605,7 +630,7 @@ __global__ __launch_bounds__(1024) void k_chainC(const ProbDev* __restrict__ pro
     #pragma unroll
                 for (int q = 0; q < RQ; ++q) {
                     float2 y = yl[q];
-                    if (MODE == MODE_BWD) y = csub<float>(uold[q], y);
+                    if constexpr (MODE == MODE_BWD) y = csub<float>(uold[q], y);
                     if (col5 < n && q < ch.nq)
                         gst(uout + (int64_t)(ch.rhs0 + q) * N + (int64_t)(jl - 1) * n + col5, cvt_out<TO, float>(y));
                     gs[cc5 * RQ + q] = y;

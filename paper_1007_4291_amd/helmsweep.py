@@ -201,7 +201,7 @@ class Problem:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:     # (module globals are gone at interpreter exit)
             _lib.helm_free(h)
             self._h = None
 
@@ -276,7 +276,7 @@ class Factors:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:     # (module globals are gone at interpreter exit)
             _lib.sweep_free(h)
             self._h = None
 
@@ -433,7 +433,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:     # (module globals are gone at interpreter exit)
             _lib.helm_batch_free(h)
             self._h = None
 
