@@ -64,7 +64,11 @@ template <class TF, int BS, int SEG>
 __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __restrict__ probs,
                                                            const CompDev* __restrict__ work) {
     using SH = CompShape<BS, SEG>;
-    constexpr int P = SEG + BS;                       // unit inputs: gamma_0..gamma_{SEG-1}, c_in e_0..e_{B-1}
+    // Unit inputs, in this order: c_in e_0..e_{B-1} (columns 0..B-1), then gamma_0..gamma_{SEG-1}
+    // (columns B..P-1).  gamma_j enters at local step j, so before it its column of z is zero: at
+    // step j only the first B + j + 1 columns are nonzero, and every product below is restricted to
+    // the 3-column tiles that reach into them (the others would add exact zeros).
+    constexpr int P = SEG + BS;
     constexpr int PT = (P + 2) / 3 * 3;               // ... padded to whole triples of columns (zero columns)
     constexpr int TT = PT / 3;
     constexpr int NGT = TT * (TT + 1) / 2;            // 3 x 3 tiles of the upper triangle of the symmetric G
@@ -87,19 +91,17 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
 
     for (int e = tid; e < BS * PT; e += COMP_THREADS) {
         const int r = e / PT, p = e - (e / PT) * PT;
-        zs[r][p] = make_double2((p >= SEG && p < P && p - SEG == r) ? 1.0 : 0.0, 0.0);
+        zs[r][p] = make_double2(p == r ? 1.0 : 0.0, 0.0);
     }
     for (int e = tid; e < 2 * SEG; e += COMP_THREADS) cpl[e >> 1][e & 1] = make_float2(0.f, 0.f);
     // register tiles: the G tile (rows 3 gi .., columns 3 gj ..) and the y tile (row yr, columns 3 yt ..)
-    // of this thread, so that every LDS value read feeds three multiply-adds
-    int gi = 0, gj = 0;
-    if (tid < NGT) {
-        int g = tid, a = 0;
-        while (g >= TT - a) { g -= TT - a; ++a; }
-        gi = a;
-        gj = a + g;
-    }
-    const int yr = tid / TT, yt = tid - (tid / TT) * TT;
+    // of this thread, so that every LDS value read feeds three multiply-adds.  Both are numbered so
+    // that the tiles in use at a step are those of the lowest thread indices: y tiles by column tile,
+    // G tiles by column tile gj, then row tile gi <= gj.
+    int gj = 0;
+    while ((gj + 1) * (gj + 2) / 2 <= tid) ++gj;
+    const int gi = tid - gj * (gj + 1) / 2;
+    const int yt = tid / BS, yr = tid - (tid / BS) * BS;
     double2 gacc[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -117,6 +119,7 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
     for (int j = 0; j < SEG; ++j) {
         const int t = tb + j;
         if (t < 0 || t >= n) continue;                 // columns past the strip's edge (uniform)
+        const int ta = (BS + j + 1 + 2) / 3;           // column tiles with a nonzero column at this step
         const HS_GLOBAL C2<TF>* col = fac + (int64_t)t * STRIDE;
         if (tid < PACK) {
             const C2<TF> v = gld(col + tid);
@@ -133,10 +136,10 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
             cpl[j][0] = make_float2((float)a.x, (float)a.y);
             cpl[j][1] = make_float2((float)b.x, (float)b.y);
         }
-        if (tid == 0) zs[SLOT][j] = make_double2(1.0, 0.0);   // gamma_j enters at its own step
+        if (tid == 0) zs[SLOT][BS + j] = make_double2(1.0, 0.0);   // gamma_j enters at its own step
         __syncthreads();
         // y = Lambda^{-1} z, a row and three columns per thread
-        if (tid < BS * TT) {
+        if (yt < ta) {
             double2 acc[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[c] = make_double2(0.0, 0.0);
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
         }
         __syncthreads();
         // G += z^T y over the step, a 3 x 3 tile per thread
-        if (tid < NGT) {
+        if (gj < ta) {
 #pragma unroll 2
             for (int r = 0; r < BS; ++r) {
                 double2 za[3], yb[3];
@@ -167,8 +170,8 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
             }
         }
         __syncthreads();
-        for (int e = tid; e < BS * PT; e += COMP_THREADS) {
-            const int r = e / PT, p = e - (e / PT) * PT;
+        for (int e = tid; e < BS * 3 * ta; e += COMP_THREADS) {
+            const int r = e / (3 * ta), p = e - r * (3 * ta);
             zs[r][p] = cmul<double>(ne[r], ys[r][p]);
         }
         __syncthreads();
@@ -188,6 +191,7 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
             }
     }
     __syncthreads();
+    // the stored blocks; gamma_j is column BS + j, c_in entry k is column k
     HS_GLOBAL float2* out = gptr((float2*)W.out);
     auto zf = [&](int r, int p) -> float2 { return make_float2((float)zs[r][p].x, (float)zs[r][p].y); };
     const float2 zero = make_float2(0.f, 0.f);
@@ -195,19 +199,18 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
         float2 v = zero;
         if (e < SH::O_G2) {
             const int j = e / SH::R1P, i = e - j * SH::R1P;
-            if (i < BS) v = zf(i, j);                                   // QF[i][j]
-            else if (i < 2 * BS) v = gram[SEG + i - BS][j];             // QB[i-B][j]
-            else if (i < SH::R1) v = gram[i - 2 * BS][j];               // KS[i-2B][j]
+            if (i < BS) v = zf(i, BS + j);                              // QF[i][j]
+            else if (i < 2 * BS) v = gram[i - BS][BS + j];              // QB[i-B][j]
+            else if (i < SH::R1) v = gram[i - BS][BS + j];              // KS[i-2B][j]: gamma row i - 2B
         } else if (e < SH::O_G3) {
             const int k = (e - SH::O_G2) / SH::R2P, i = (e - SH::O_G2) - k * SH::R2P;
-            if (i < BS) v = gram[SEG + i][SEG + k];                     // W[i][k]
-            else if (i < SH::R2) v = gram[i - BS][SEG + k];             // VS[i-B][k]
+            if (i < SH::R2) v = gram[i][k];                             // W[i][k] (i < B), VS[i-B][k]
         } else if (e < SH::O_PHI) {
             const int k = (e - SH::O_G3) / SH::R3P, jj = (e - SH::O_G3) - k * SH::R3P;
-            if (jj < SEG) v = zf(k, jj);                                // US[jj][k] = QF[k][jj]
+            if (jj < SEG) v = zf(k, BS + jj);                           // US[jj][k] = QF[k][jj]
         } else if (e < SH::O_CPL) {
             const int r = (e - SH::O_PHI) / BS, k = (e - SH::O_PHI) - r * BS;
-            v = zf(r, SEG + k);                                         // Phi[r][k]
+            v = zf(r, k);                                               // Phi[r][k]
         } else if (e < SH::O_CPL + 2 * SEG) {
             const int q = e - SH::O_CPL;
             v = cpl[q >> 1][q & 1];
