@@ -114,30 +114,42 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
         while (e >= BS - pr) { e -= BS - pr; ++pr; }
         pk = pr + e;
     }
+    // the steps inside the strip (the others are columns past its edge); each step's column of the
+    // factor is loaded into registers one step ahead, under the previous step's products
+    const int j_lo = tb < 0 ? -tb : 0, j_hi = n - tb < SEG ? n - tb : SEG;
+    double2 is2 = make_double2(0.0, 0.0);
+    if (tid >= PACK && tid < PACK + BS) is2 = gld(gptr(W.ris2 + W.rstep * (tid - PACK)));
+    // this thread's entries of a column: the packed inverse (tid < PACK), -E (next BS), the two layer-row
+    // couplings (one thread); the others re-read entry 0
+    const int fo0 = tid < PACK ? tid : tid < PACK + BS ? PACK + XCOL_E : tid == PACK + BS ? PACK + XCOL_APREV : 0;
+    const int fo1 = tid == PACK + BS ? PACK + XCOL_ANEXT : 0;
+    C2<TF> pf0 = {}, pf1 = {};
+    if (j_lo < j_hi) {
+        const HS_GLOBAL C2<TF>* col = fac + (int64_t)(tb + j_lo) * STRIDE;
+        pf0 = gld(col + fo0);
+        pf1 = gld(col + fo1);
+    }
     __syncthreads();
 
-    for (int j = 0; j < SEG; ++j) {
-        const int t = tb + j;
-        if (t < 0 || t >= n) continue;                 // columns past the strip's edge (uniform)
+    for (int j = j_lo; j < j_hi; ++j) {
         const int ta = (BS + j + 1 + 2) / 3;           // column tiles with a nonzero column at this step
-        const HS_GLOBAL C2<TF>* col = fac + (int64_t)t * STRIDE;
         if (tid < PACK) {
-            const C2<TF> v = gld(col + tid);
-            const double2 d = make_double2((double)v.x, (double)v.y);
+            const double2 d = make_double2((double)pf0.x, (double)pf0.y);
             lam[pr][pk] = d;
             lam[pk][pr] = d;
         } else if (tid < PACK + BS) {
-            const int r = tid - PACK;
-            const C2<TF> e = gld(col + PACK + XCOL_E);
-            const double2 is2 = gld(gptr(W.ris2 + W.rstep * r));
-            ne[r] = cscale<double>(cmul<double>(make_double2((double)e.x, (double)e.y), is2), -1.0);
+            ne[tid - PACK] = cscale<double>(cmul<double>(make_double2((double)pf0.x, (double)pf0.y), is2), -1.0);
         } else if (tid == PACK + BS) {
-            const C2<TF> a = gld(col + PACK + XCOL_APREV), b = gld(col + PACK + XCOL_ANEXT);
-            cpl[j][0] = make_float2((float)a.x, (float)a.y);
-            cpl[j][1] = make_float2((float)b.x, (float)b.y);
+            cpl[j][0] = make_float2((float)pf0.x, (float)pf0.y);
+            cpl[j][1] = make_float2((float)pf1.x, (float)pf1.y);
         }
         if (tid == 0) zs[SLOT][BS + j] = make_double2(1.0, 0.0);   // gamma_j enters at its own step
         __syncthreads();
+        if (j + 1 < j_hi) {
+            const HS_GLOBAL C2<TF>* col = fac + (int64_t)(tb + j + 1) * STRIDE;
+            pf0 = gld(col + fo0);
+            pf1 = gld(col + fo1);
+        }
         // y = Lambda^{-1} z, a row and three columns per thread
         if (yt < ta) {
             double2 acc[3];

@@ -49,8 +49,9 @@ __global__ __launch_bounds__(64) void k_factor(const ProbDev* __restrict__ probs
     constexpr int RP = RowsOf<BS>::RP, Q = RowsOf<BS>::Q;
     constexpr int PACK = packed_size(BS);
     constexpr int STRIDE = col_stride<TS>(BS);
-    __shared__ double2 inv_lds[Q][BS][BS + 1];     // Gauss-Jordan result of this step
-    __shared__ double2 sym_lds[Q][BS][BS + 1];     // symmetrised inverse (of the previous step while building)
+    // Gauss-Jordan result of this step, then (upper triangle, in place) the symmetrised inverse, which
+    // the next step reads while building its Lambda
+    __shared__ double2 sym_lds[Q][BS][BS + 1];
     __shared__ double2 prow[Q][BS];                // pivot row of the current elimination step
     __shared__ double2 e_lds[Q][BS];
     __shared__ double2 extra[Q][3];
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(64) void k_factor(const ProbDev* __restrict__ probs
             if (k == r) v = d;
             else if (k == r - 1) v = ayl;
             else if (k == r + 1) v = ayh;
-            if (s > 0) v = cfms<double>(cmul<double>(e, e_lds[g][k]), sym_lds[g][rc][k], v);
+            if (s > 0) v = cfms<double>(cmul<double>(e, e_lds[g][k]), sym_lds[g][rc < k ? rc : k][rc < k ? k : rc], v);
             slot[k] = active ? v : zero;
         }
 
@@ -162,10 +163,7 @@ __global__ __launch_bounds__(64) void k_factor(const ProbDev* __restrict__ probs
                 for (int q = 0; q < BS; ++q) prow[g][q] = slot[q];
             }
             wave_sync();
-            double2 pr[BS];
-#pragma unroll
-            for (int q = 0; q < BS; ++q) pr[q] = prow[g][q];
-            const double2 a = pr[k];
+            const double2 a = prow[g][k];
             const double a2 = a.x * a.x + a.y * a.y;
             bad |= (a2 > 0.0 && a2 <= DBL_MAX) ? 0 : 1;
             const double ia2 = 1.0 / a2;
@@ -176,23 +174,26 @@ __global__ __launch_bounds__(64) void k_factor(const ProbDev* __restrict__ probs
 #pragma unroll
             for (int q = 0; q < BS; ++q) {
                 if (q == k) continue;
-                slot[q] = cfms<double>(f, pr[q], make_double2(slot[q].x * keep, slot[q].y * keep));
+                slot[q] = cfms<double>(f, prow[g][q], make_double2(slot[q].x * keep, slot[q].y * keep));
             }
             slot[k] = make_double2(-f.x, -f.y);
             myrow = me ? k : myrow;
             used = used || me;
             wave_sync();
         }
-        // lane p_k holds row k of the inverse: slot[q] = Inv[k][p_q]
+        // lane p_k holds row k of the inverse: slot[q] = Inv[k][p_q] (the previous inverse has been read)
         if (active) {
 #pragma unroll
-            for (int q = 0; q < BS; ++q) inv_lds[g][myrow][piv[q]] = slot[q];
+            for (int q = 0; q < BS; ++q) sym_lds[g][myrow][piv[q]] = slot[q];
         }
         wave_sync();
+        // symmetrise into the upper triangle: lane r writes only (r, k >= r) and reads (k, r) below the
+        // diagonal, which no lane writes
         if (active) {
 #pragma unroll
             for (int k = 0; k < BS; ++k) {
-                const double2 x = inv_lds[g][r][k], y = inv_lds[g][k][r];
+                if (k < r) continue;
+                const double2 x = sym_lds[g][r][k], y = sym_lds[g][k][r];
                 sym_lds[g][r][k] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y + y.y));
             }
         }
