@@ -75,13 +75,20 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
     constexpr int PACK = packed_size(BS), STRIDE = col_stride<TF>(BS);
     constexpr int SLOT = BS - 1;                      // the layer row (local row order)
     static_assert(NGT <= COMP_THREADS && BS * TT <= COMP_THREADS, "one thread per tile");
-    // LDS: the z and y = Lambda^{-1} z vectors of all unit inputs (FP64), the step's Lambda^{-1}, -E/s2
-    __shared__ double2 zs[BS][PT];
-    __shared__ double2 ys[BS][PT];
-    __shared__ double2 lam[BS][BS];
-    __shared__ double2 ne[BS];                        // -E_t / s2 of each row for the current step
+    // LDS: the z vectors of all unit inputs (FP64, two buffers: this step's and the next step's), y =
+    // Lambda^{-1} z, the step's Lambda^{-1} and -E/s2 (two buffers each: the next column's are written
+    // while this one's are read), the layer-row couplings; after the steps G (FP32) takes the place of
+    // the second z buffer and y
+    constexpr int ZB = BS * PT;                       // complex FP64 values per z / y buffer
+    constexpr int GB = (P * (P + 1) + 1) / 2;         // G in complex FP64 units
+    constexpr int ZYN = 3 * ZB > ZB + GB ? 3 * ZB : ZB + GB;
+    __shared__ double2 zyb[ZYN];                      // z[0], z[1], y; then z[0], G
+    __shared__ double2 lam2[2][BS][BS];
+    __shared__ double2 ne2[2][BS];
     __shared__ float2 cpl[SEG][2];
-    __shared__ float2 gram[P][P + 1];
+    auto zsb = [&](int b) { return reinterpret_cast<double2 (*)[PT]>(zyb + b * ZB); };
+    double2 (*const ys)[PT] = reinterpret_cast<double2 (*)[PT]>(zyb + 2 * ZB);
+    float2 (*const gram)[P + 1] = reinterpret_cast<float2 (*)[P + 1]>(zyb + ZB);
 
     const CompDev W = work[blockIdx.x];
     const int tid = threadIdx.x;
@@ -89,9 +96,13 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
     const int tb = (W.cdir > 0) ? W.seg * SEG : n - W.seg * SEG - SEG;   // LU step of local step 0
     const HS_GLOBAL C2<TF>* fac = gptr((const C2<TF>*)W.fac);
 
-    for (int e = tid; e < BS * PT; e += COMP_THREADS) {
-        const int r = e / PT, p = e - (e / PT) * PT;
-        zs[r][p] = make_double2(p == r ? 1.0 : 0.0, 0.0);
+    // the steps inside the strip (the others are columns past its edge)
+    const int j_lo = tb < 0 ? -tb : 0, j_hi = n - tb < SEG ? n - tb : SEG;
+    // z[0]: the c_in unit inputs and gamma_{j_lo}, which enters at the first step; z[1]: zero
+    for (int e = tid; e < 2 * ZB; e += COMP_THREADS) {
+        const int r = (e % ZB) / PT, p = (e % ZB) - ((e % ZB) / PT) * PT;
+        const bool one = e < ZB && (p == r || (r == SLOT && p == BS + j_lo && j_lo < j_hi));
+        zyb[e] = make_double2(one ? 1.0 : 0.0, 0.0);
     }
     for (int e = tid; e < 2 * SEG; e += COMP_THREADS) cpl[e >> 1][e & 1] = make_float2(0.f, 0.f);
     // register tiles: the G tile (rows 3 gi .., columns 3 gj ..) and the y tile (row yr, columns 3 yt ..)
@@ -114,9 +125,8 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
         while (e >= BS - pr) { e -= BS - pr; ++pr; }
         pk = pr + e;
     }
-    // the steps inside the strip (the others are columns past its edge); each step's column of the
-    // factor is loaded into registers one step ahead, under the previous step's products
-    const int j_lo = tb < 0 ? -tb : 0, j_hi = n - tb < SEG ? n - tb : SEG;
+    // each step's column of the factor is loaded into registers one step ahead, under the previous
+    // step's products
     double2 is2 = make_double2(0.0, 0.0);
     if (tid >= PACK && tid < PACK + BS) is2 = gld(gptr(W.ris2 + W.rstep * (tid - PACK)));
     // this thread's entries of a column: the packed inverse (tid < PACK), -E (next BS), the two layer-row
@@ -129,50 +139,77 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
         pf0 = gld(col + fo0);
         pf1 = gld(col + fo1);
     }
-    __syncthreads();
-
-    for (int j = j_lo; j < j_hi; ++j) {
-        const int ta = (BS + j + 1 + 2) / 3;           // column tiles with a nonzero column at this step
+    // this thread's part of loading a column into the buffers of step parity b
+    auto put_col = [&](int j, int b) __attribute__((always_inline)) {
         if (tid < PACK) {
             const double2 d = make_double2((double)pf0.x, (double)pf0.y);
-            lam[pr][pk] = d;
-            lam[pk][pr] = d;
+            lam2[b][pr][pk] = d;
+            lam2[b][pk][pr] = d;
         } else if (tid < PACK + BS) {
-            ne[tid - PACK] = cscale<double>(cmul<double>(make_double2((double)pf0.x, (double)pf0.y), is2), -1.0);
+            ne2[b][tid - PACK] = cscale<double>(cmul<double>(make_double2((double)pf0.x, (double)pf0.y), is2), -1.0);
         } else if (tid == PACK + BS) {
             cpl[j][0] = make_float2((float)pf0.x, (float)pf0.y);
             cpl[j][1] = make_float2((float)pf1.x, (float)pf1.y);
         }
-        if (tid == 0) zs[SLOT][BS + j] = make_double2(1.0, 0.0);   // gamma_j enters at its own step
-        __syncthreads();
-        if (j + 1 < j_hi) {
-            const HS_GLOBAL C2<TF>* col = fac + (int64_t)(tb + j + 1) * STRIDE;
+    };
+    __syncthreads();                                  // the initial z and couplings are in place
+    if (j_lo < j_hi) {
+        put_col(j_lo, 0);
+        if (j_lo + 1 < j_hi) {
+            const HS_GLOBAL C2<TF>* col = fac + (int64_t)(tb + j_lo + 1) * STRIDE;
             pf0 = gld(col + fo0);
             pf1 = gld(col + fo1);
         }
-        // y = Lambda^{-1} z, a row and three columns per thread
+    }
+    __syncthreads();
+
+    // Two block barriers per step: (A) y = Lambda^{-1} z and the next step's z = (-E/s2) y, with the
+    // next column's factor data going into the other buffers; (B) G += z^T y.
+    for (int j = j_lo; j < j_hi; ++j) {
+        const int cur = (j - j_lo) & 1, nx = cur ^ 1;
+        const int ta = (BS + j + 1 + 2) / 3;           // column tiles with a nonzero column at this step
+        double2 (*const zc)[PT] = zsb(cur);
+        double2 (*const zn)[PT] = zsb(nx);
+        const bool more = j + 1 < j_hi;
+        // (A) a row and three columns of y per thread, and the same entries of the next z; gamma_{j+1}
+        // enters the next z in row SLOT, column BS + j + 1
         if (yt < ta) {
             double2 acc[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[c] = make_double2(0.0, 0.0);
 #pragma unroll 4
             for (int k = 0; k < BS; ++k) {
-                const double2 l = lam[yr][k];
+                const double2 l = lam2[cur][yr][k];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) acc[c] = cfma<double>(l, zs[k][3 * yt + c], acc[c]);
+                for (int c = 0; c < 3; ++c) acc[c] = cfma<double>(l, zc[k][3 * yt + c], acc[c]);
             }
+            const double2 nr = ne2[cur][yr];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ys[yr][3 * yt + c] = acc[c];
+            for (int c = 0; c < 3; ++c) {
+                ys[yr][3 * yt + c] = acc[c];
+                const bool entry = more && yr == SLOT && 3 * yt + c == BS + j + 1;
+                zn[yr][3 * yt + c] = entry ? make_double2(1.0, 0.0) : cmul<double>(nr, acc[c]);
+            }
+        }
+        // gamma_{j+1}'s column past this step's tiles: no thread above writes it
+        if (tid == 0 && more && BS + j + 1 >= 3 * ta) zn[SLOT][BS + j + 1] = make_double2(1.0, 0.0);
+        if (more) {
+            put_col(j + 1, nx);
+            if (j + 2 < j_hi) {
+                const HS_GLOBAL C2<TF>* col = fac + (int64_t)(tb + j + 2) * STRIDE;
+                pf0 = gld(col + fo0);
+                pf1 = gld(col + fo1);
+            }
         }
         __syncthreads();
-        // G += z^T y over the step, a 3 x 3 tile per thread
+        // (B) G += z^T y over the step, a 3 x 3 tile per thread
         if (gj < ta) {
 #pragma unroll 2
             for (int r = 0; r < BS; ++r) {
                 double2 za[3], yb[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    za[c] = zs[r][3 * gi + c];
+                    za[c] = zc[r][3 * gi + c];
                     yb[c] = ys[r][3 * gj + c];
                 }
 #pragma unroll
@@ -182,12 +219,13 @@ __global__ __launch_bounds__(COMP_THREADS) void k_compress(const ProbDev* __rest
             }
         }
         __syncthreads();
-        for (int e = tid; e < BS * 3 * ta; e += COMP_THREADS) {
-            const int r = e / (3 * ta), p = e - r * (3 * ta);
-            zs[r][p] = cmul<double>(ne[r], ys[r][p]);
-        }
+    }
+    // the final z (after the last step) into buffer 0, so that G can take buffer 1 and y
+    if ((j_hi - j_lo) & 1) {
+        for (int e = tid; e < ZB; e += COMP_THREADS) zyb[e] = zyb[ZB + e];
         __syncthreads();
     }
+    double2 (*const zs)[PT] = zsb(0);
     // G's upper triangle (a <= b) from the tiles, mirrored
     if (tid < NGT) {
 #pragma unroll
