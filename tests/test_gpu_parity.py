@@ -550,6 +550,32 @@ def test_sweep_compressed_parity(hs, torch, monkeypatch, n, w, cseg, crq):
     _check_apply(ub[1].cpu().numpy(), OS.apply_sweep(OS.factor(op2, c2), f2), n2, TOL_C64, "batch 1")
 
 
+def test_sweep_compressed_deterministic(hs, torch, monkeypatch):
+    """Factorisation, compression and the compressed chains have no atomics and no order-dependent sums,
+    so repeated factorisations and applications give the same bits: a race between the threads of
+    k_compress (z, Lambda^-1 and -E/s2 are double-buffered across its steps) or between the waves of
+    k_chainC (hand-off by ready flags) would show up here as differing results.  n = 511 (16 segments
+    per strip, the bench's largest chains), both sweep directions of every strip parity."""
+    monkeypatch.setenv("HELM_SWEEP_KIND", "2")
+    monkeypatch.setenv("HELM_CSEG", "32")
+    monkeypatch.setenv("HELM_CRQ", "4")
+    n, w = 511, 12
+    op = OH.Params(n=n, omega=2 * math.pi * n / 8, alpha=2.0, pml_w=w, mpml_w=w)
+    c = workloads.velocity_layered(n, seed=23)
+    A = _gpu_problem(hs, torch, op, c)
+    fd = torch.as_tensor(workloads.random_rhs(n, 8, seed=29), device="cuda").to(torch.complex64)
+    ref = None
+    for rep in range(3):
+        F = hs.Factors(A, hs.HELM_C64)
+        for _ in range(2):
+            u = F.apply(fd).cpu().numpy()
+            if ref is None:
+                ref = u
+            _log(f"  factorisation {rep}: max |u - u_0| = {np.abs(u - ref).max():.3e}")
+            assert np.array_equal(u, ref)
+        del F
+
+
 def test_sweep_compressed_fgmres(hs, torch, monkeypatch):
     """Batched FGMRES with the compressed chains takes the segmented chains' iterations (+-1) and both
     solutions meet the 1e-6 true residual."""
