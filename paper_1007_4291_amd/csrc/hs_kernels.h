@@ -114,7 +114,7 @@ struct SysVec {
     int64_t len, vstride, zstride;
 };
 
-constexpr int KR_TILE = 1024;
+constexpr int KR_TILE = 2048;
 constexpr int KR_THREADS = 256;
 
 // All tile kernels skip the tiles of systems with active[s] == 0 (active may be nullptr: all active).
